@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs for the second-Born / GKBA collision-integral path.
+
+This module only draws random numbers and builds input tensors (h, v, rho
+history) with the structure the method expects.  It holds none of the method's
+arithmetic: no propagator, no GKBA two-time function, no self-energy, no
+collision integral.  Both the FP64 oracle's tests and the HIP path's tests and
+benchmark take their inputs from here, so the two see identical bits.
+
+Structure of the inputs (the paper's model, Sec. II):
+  * h      -- one-body Hermitian matrix h_ij (Eq. 1-2).  Here (X + X^dag)/2 with
+              X_ij = a + ib, a, b ~ N(0, 1): E|h_ij|^2 = 1 off the diagonal and a
+              real N(0, 1) diagonal.
+  * v      -- real two-body tensor v_ijkl (Eq. 3).  For a real basis it has the
+              8-fold permutation symmetry of Eq. 4; the generator builds a dense
+              tensor with the sub-group {ijkl, jilk, klij, lkji} of it:
+              X_ijkl = sum_g A_ig A_jg B_kg B_lg, v = (X + X_klij)/2, scaled to
+              max|v| = 0.5.  A "generic" variant averages an i.i.d. Gaussian
+              tensor over that sub-group instead (no low-rank structure).
+  * rho    -- one-particle density matrix, Hermitian with eigenvalues in [0, 1]
+              and trace N/2 (rho = -i G^<(t,t), Sec. II).  Eigenvalues come in
+              pairs (u, 1-u) with u ~ U[0,1] (plus 0.5 when N is odd), rotated by
+              a Haar unitary.
+  * history -- rho_k for k = 0..T-1.  "smooth": rho_k = R_k rho_0 R_k^dag with
+              R_k a seeded unitary path exp(-i H k dt) for an independent random
+              Hermitian H (so the spectrum and trace stay fixed and the history
+              is as smooth as a real propagation); "iid": an independent rho per k.
+
+Seeds: numpy Generator(PCG64(SeedSequence([1905, 1180, config, system, stream]))).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+
+SEED_PREFIX = (1905, 1180)
+DT_DEFAULT = 0.05
+
+# stream ids: one independent random stream per generated object
+_S_H, _S_V, _S_RHO0, _S_HIST, _S_DIR = 0, 1, 2, 3, 4
+
+
+def rng(config_id: int, system_id: int, stream_id: int) -> np.random.Generator:
+    """Independent, reproducible random stream for one generated object."""
+    ss = np.random.SeedSequence([*SEED_PREFIX, int(config_id), int(system_id), int(stream_id)])
+    return np.random.Generator(np.random.PCG64(ss))
+
+
+def hermitian_gaussian(n: int, g: np.random.Generator) -> np.ndarray:
+    x = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    return 0.5 * (x + x.conj().T)
+
+
+def interaction_lowrank(n: int, g: np.random.Generator, vmax: float = 0.5) -> np.ndarray:
+    """Dense real v_ijkl with v_ijkl = v_jilk = v_klij = v_lkji, max|v| = vmax."""
+    a = g.standard_normal((n, n))
+    b = g.standard_normal((n, n))
+    aa = (a[:, None, :] * a[None, :, :]).reshape(n * n, n)      # (ij, g)
+    bb = (b[:, None, :] * b[None, :, :]).reshape(n * n, n)      # (kl, g)
+    x = (aa @ bb.T).reshape(n, n, n, n)                          # X_ijkl
+    v = 0.5 * (x + x.transpose(2, 3, 0, 1))                      # + X_klij
+    v *= vmax / np.abs(v).max()
+    return np.ascontiguousarray(v)
+
+
+def interaction_generic(n: int, g: np.random.Generator, vmax: float = 0.5) -> np.ndarray:
+    """Full-rank real v averaged over the sub-group {ijkl, jilk, klij, lkji}."""
+    x = g.standard_normal((n, n, n, n))
+    v = 0.25 * (x + x.transpose(1, 0, 3, 2) + x.transpose(2, 3, 0, 1) + x.transpose(3, 2, 1, 0))
+    v *= vmax / np.abs(v).max()
+    return np.ascontiguousarray(v)
+
+
+def haar_unitary(n: int, g: np.random.Generator) -> np.ndarray:
+    z = (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    d = np.diagonal(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def density_matrix(n: int, g: np.random.Generator) -> np.ndarray:
+    """Hermitian rho with eigenvalues uniform in [0,1] and trace exactly n/2."""
+    u = g.uniform(0.0, 1.0, size=n // 2)
+    lam = np.concatenate([u, 1.0 - u, [0.5] if n % 2 else []])
+    q = haar_unitary(n, g)
+    rho = (q * lam[None, :]) @ q.conj().T
+    return 0.5 * (rho + rho.conj().T)
+
+
+def _unitary_path(hr: np.ndarray, taus: np.ndarray) -> np.ndarray:
+    e, p = np.linalg.eigh(hr)
+    ph = np.exp(-1j * e[None, :] * taus[:, None])                # (K, n)
+    return np.einsum("ia,ka,ja->kij", p, ph, p.conj())
+
+
+def rho_history(n: int, t: int, dt: float, g: np.random.Generator, kind: str = "smooth") -> np.ndarray:
+    if kind == "iid":
+        return np.stack([density_matrix(n, g) for _ in range(t)])
+    if kind != "smooth":
+        raise ValueError(f"unknown history kind {kind!r}")
+    rho0 = density_matrix(n, g)
+    hr = hermitian_gaussian(n, g)
+    r = _unitary_path(hr, dt * np.arange(t, dtype=np.float64))
+    hist = r @ rho0[None] @ r.conj().transpose(0, 2, 1)
+    return np.ascontiguousarray(0.5 * (hist + hist.conj().transpose(0, 2, 1)))
+
+
+@dataclasses.dataclass
+class System:
+    """One synthetic GKBA system: frozen h, dense real v, rho history, dt."""
+    n: int
+    t: int
+    dt: float
+    h: np.ndarray          # (n, n) complex128, Hermitian
+    v: np.ndarray          # (n, n, n, n) float64
+    rho_hist: np.ndarray   # (t, n, n) complex128, rho_hist[k] = rho(k dt)
+
+    @property
+    def flops(self) -> float:
+        """Algorithmic real flops of one collision-integral evaluation (48 T N^5)."""
+        return 48.0 * self.t * float(self.n) ** 5
+
+
+def make_system(n: int, t: int, config_id: int = 0, system_id: int = 0, dt: float = DT_DEFAULT,
+                v_kind: str = "lowrank", hist_kind: str = "smooth") -> System:
+    h = hermitian_gaussian(n, rng(config_id, system_id, _S_H))
+    gv = rng(config_id, system_id, _S_V)
+    v = interaction_lowrank(n, gv) if v_kind == "lowrank" else interaction_generic(n, gv)
+    hist = rho_history(n, t, dt, rng(config_id, system_id, _S_HIST), hist_kind)
+    return System(n=n, t=t, dt=dt, h=h, v=v, rho_hist=hist)
+
+
+# The five workloads: (config id, N, T).  Config 4 is a batch of 32 systems.
+CONFIGS = {
+    0: dict(n=10, t=20),      # plain method, oracle in full
+    1: dict(n=50, t=500),     # FP64 baseline
+    2: dict(n=100, t=1000),   # precision workload (headline)
+    3: dict(n=64, t=256),     # differentiation
+}
+
+
+def make_config(config_id: int, **kw) -> System:
+    return make_system(config_id=config_id, **CONFIGS[config_id], **kw)
+
+
+def batch_shapes(nsys: int = 32, config_id: int = 4) -> List[tuple]:
+    """(N_b, T_b) for the batched workload: N ~ U{24..96}, T ~ U{64..512}."""
+    g = rng(config_id, 0, _S_DIR)
+    ns = g.integers(24, 97, size=nsys)
+    ts = g.integers(64, 513, size=nsys)
+    return [(int(a), int(b)) for a, b in zip(ns, ts)]
+
+
+def make_batch(nsys: int = 32, config_id: int = 4, shapes=None) -> List[System]:
+    shapes = shapes if shapes is not None else batch_shapes(nsys, config_id)
+    return [make_system(n, t, config_id=config_id, system_id=i + 1) for i, (n, t) in enumerate(shapes)]
+
+
+def hermitian_directions(n: int, count: int, seed: int = 0) -> np.ndarray:
+    g = rng(3, seed, _S_DIR)
+    return np.stack([hermitian_gaussian(n, g) for _ in range(count)])
