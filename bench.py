@@ -1,0 +1,219 @@
+#!/usr/bin/env python
+"""Benchmark of the GKBA collision integral I(t) on one MI355X.
+
+Workload: N = 100 basis functions, T = 1000 past times, dt = 0.05, seeded
+synthetic inputs (dense real v of 10^8 entries with the {ijkl, jilk, klij,
+lkji} permutation symmetry, Hermitian h, smooth rho history).  One step = one
+full I(t) evaluation through the C ABI: propagators, GKBA two-time functions,
+2 T second-Born self-energies (48 T N^5 = 4.8e14 algorithmic flops) and the
+float64 sum over past times, with all inputs resident in HBM.
+
+Prints one JSON line.  `value` is steps/s of the bulk precision given by
+--prec (default: the split-float16 path); the float64 and float32 paths are
+timed beside it for the "vs FP64" comparison.  The roofline object refers to
+the dominant contraction kernel, timed with HIP events on the launch stream
+over the timed region.  The CPU baseline is the FP64 oracle on a bounded
+sample of past times, scaled to a full step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GKBA collision-integral steps/s + MFMA TFLOP/s (N=100,T=1000) vs FP64, at rel err"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16x3": 2516.0}   # MI355X dense matrix peaks
+STAGES = ["R1", "R2", "R3", "R4", "layout", "gkba", "pack+reduce", "collision"]
+# algorithmic real flops per slice (one self-energy) and stage: complex x real = 4, complex x complex = 8
+STAGE_FLOPS_PER_N5 = {"R1": 4, "R2": 8, "R3": 8, "R4": 4}
+KERNEL_SOURCES = ["paper_1905_01180_amd/csrc/gemm.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def rel_f(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cpu_baseline(sys_, nsample: int):
+    """FP64 oracle on `nsample` past times, scaled to one full step (T past times)."""
+    from oracle import sb2_oracle as o
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(i.get("num_threads", 1)) for i in threadpool_info()) if threadpool_info() else os.cpu_count()
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    t_len, n = sys_.t, sys_.n
+    ks = [t_len - 1 - i * max(1, t_len // max(nsample, 1)) for i in range(nsample)]
+    w = o.exchange_combined(sys_.v)
+    zero = np.zeros((n, n), np.complex128)
+    t0 = time.perf_counter()
+    for k in ks:
+        u = o.propagator(sys_.h, (t_len - k) * sys_.dt)
+        gl, gg, glb, ggb = o.gkba_pair(u, sys_.rho_hist[k], zero)
+        o.sigma(sys_.v, gg, glb, w) @ glb - o.sigma(sys_.v, gl, ggb, w) @ ggb
+    dt_s = time.perf_counter() - t0
+    per_step = dt_s / len(ks) * t_len
+    return {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{len(ks)} of {t_len} past times (Sigma^<, Sigma^>, collision term each) at N={n}, "
+                      f"{dt_s:.1f} s, scaled by T/{len(ks)} (cost is linear in T)",
+            "seconds_per_step": per_step}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp16x3", choices=["fp64", "fp32", "fp16x3"])
+    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--t", type=int, default=1000)
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other precisions")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=2)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method shards over past times with one all-reduce of I per step; not built here).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1905_01180_amd import _lib
+    from paper_1905_01180_amd import inputs as gen
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    L = _lib.lib()
+
+    cid = 2 if (args.n, args.t) == (100, 1000) else 99
+    log(f"generating inputs N={args.n} T={args.t}")
+    s = gen.make_system(args.n, args.t, config_id=cid)
+    v = torch.from_numpy(s.v).to(dev)
+    h = torch.from_numpy(s.h).to(dev)
+    rho = torch.from_numpy(s.rho_hist).to(dev)
+    n5 = float(args.n) ** 5
+    flops_step = 48.0 * args.t * n5
+
+    def run(prec):
+        return _lib.sb2_collision(v, h, rho, s.dt, prec)
+
+    def timed(prec, steps, warmup, profile):
+        for _ in range(warmup):
+            run(prec)
+        torch.cuda.synchronize()
+        if profile:
+            L.sb2_profile_enable(1)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            run(prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        stages = None
+        if profile:
+            import ctypes
+            ms = (ctypes.c_double * 8)()
+            cnt = (ctypes.c_int * 8)()
+            st = L.sb2_profile_read(ms, cnt, 8)
+            L.sb2_profile_enable(0)
+            if st == 0:
+                stages = {STAGES[i]: {"ms_per_step": ms[i] / steps, "launches_per_step": cnt[i] / steps}
+                          for i in range(8)}
+        return el, stages
+
+    log(f"timing {args.prec}: warmup {args.warmup}, steps {args.steps}")
+    el, stages = timed(args.prec, args.steps, args.warmup, True)
+    value = args.steps / el
+    ms_per_step = 1e3 * el / args.steps
+
+    # dominant contraction kernel
+    roof = None
+    if stages:
+        dom = max(("R1", "R2", "R3", "R4"), key=lambda k: stages[k]["ms_per_step"])
+        st = stages[dom]
+        per_launch_ms = st["ms_per_step"] / max(st["launches_per_step"], 1e-9)
+        flops_per_launch = STAGE_FLOPS_PER_N5[dom] * n5 * 2 * args.t / st["launches_per_step"]
+        achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[args.prec]
+        traffic = None
+        tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.prec}_n{args.n}.json")
+        if os.path.exists(tf):
+            with open(tf) as fh:
+                tj = json.load(fh)
+            if tj.get("kernel_hash") == kernel_hash():
+                traffic = tj.get("bytes_per_launch")
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic, "kernel": dom, "launch_ms": per_launch_ms,
+                "flops_per_launch": flops_per_launch}
+        if args.prec == "fp16x3":
+            roof["note"] = ("algorithmic flops vs the dense fp16 peak; each real product costs three fp16 "
+                            "MFMAs, so the split method's ceiling is frac = 1/3")
+
+    # accuracy against the stored FP64 oracle (written by tests/golden/make_golden.py)
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_c{cid}.npz")
+    if os.path.exists(gold):
+        z = np.load(gold)
+        got, sig = _lib.sb2_collision(v, h, rho, s.dt, args.prec, return_sigma=True)
+        got, sig = got.cpu().numpy(), sig.cpu().numpy()
+        ks = z["sigma_ks"]
+        err = {"I_rel_F": rel_f(got, z["i_ns"]),
+               "I_rel_maxabs": float(np.abs(got - z["i_ns"]).max() / np.abs(z["i_ns"]).max()),
+               "sigma_rel_F_max": max(max(rel_f(sig[0, k], z["sigma_less"][i]),
+                                          rel_f(sig[1, k], z["sigma_great"][i])) for i, k in enumerate(ks)),
+               "sigma_ks": [int(k) for k in ks],
+               "kappa_I": float(z["term_norms"].sum() / np.linalg.norm(z["i_ns"]))}
+        del sig
+
+    compare = {}
+    if not args.no_compare:
+        for p in ("fp64", "fp32", "fp16x3"):
+            if p == args.prec:
+                compare[p] = value
+                continue
+            log(f"timing {p} for comparison")
+            e2, _ = timed(p, 1, 1, False)
+            compare[p] = 1.0 / e2
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle sample")
+        cpu = cpu_baseline(s, args.cpu_sample)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": f"GKBA collision integral, N={args.n} basis, T={args.t} past times, dt={s.dt}",
+                   "N": args.n, "T": args.t, "prec": args.prec},
+        "tflops_algorithmic": flops_step * value / 1e12,
+        "roofline": roof, "cpu_baseline": cpu, "rel_err": err, "steps_per_s_by_prec": compare or None,
+        "stages": stages, "kernel_hash": kernel_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

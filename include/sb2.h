@@ -1,0 +1,180 @@
+/* sb2 -- second-Born self-energy and GKBA collision integral on MI355X (gfx950).
+ *
+ * C ABI of the library libsb2.so.  Method: Tuovinen, Covito & Sentef,
+ * "Efficient computation of the second-Born self-energy using tensor-contraction
+ * operations" (arXiv:1905.01180).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Pointers named v, h, G*, S*, rho*, I*, g* are DEVICE pointers owned by the
+ *    caller.  ws is a caller-owned device workspace of at least
+ *    sb2_workspace_size(...) bytes, 256-byte aligned.  The library allocates no
+ *    memory, creates no streams and never synchronises the device inside these
+ *    calls: all work is enqueued on `stream` (a hipStream_t passed as void*;
+ *    NULL is the default stream) and the call returns once it is enqueued.
+ *  * Complex matrices are row-major, interleaved (re, im) float64 pairs (the
+ *    layout of a C99 double complex / torch.complex128 tensor).  An N x N matrix
+ *    X has X_ij at element i*N + j.  Stacks of matrices are contiguous.
+ *  * v is the real two-body tensor v_ijkl of Eq. 3, float64, element
+ *    ((i*N + j)*N + k)*N + l.  No permutation symmetry of v is assumed unless
+ *    an entry point says so.
+ *  * Time grid: past times t_k = k*dt for k = 0..T-1; "now" is t = T*dt.
+ *    rho_hist[k] = rho(t_k), the one-particle density matrix -i G^<(t_k, t_k).
+ *  * Return value: SB2_OK or a negative sb2_status.  Argument errors are
+ *    detected on the host before anything is enqueued (outputs untouched).
+ *    A HIP launch failure returns SB2_EHIP; asynchronous device faults surface
+ *    through the HIP runtime on the caller's next synchronisation.
+ *  * Inputs are assumed Hermitian where the physics says so (h, rho_k); NaN or
+ *    Inf inputs propagate to the outputs.
+ *  * prec selects the arithmetic of the bulk tensor contractions only.  The
+ *    propagators, GKBA two-time functions, the sum over past times and every
+ *    output stay float64:
+ *      SB2_FP64        complex float64 on the FP64 matrix cores,
+ *      SB2_FP32        complex float32 on the FP32 matrix cores, float32 sums
+ *                      folded into float64 along the long contraction,
+ *      SB2_SPLIT_FP16  each float32 operand split into two scaled float16 pieces,
+ *                      three float16 products per real product (hi*hi + hi*lo +
+ *                      lo*hi) with float32 accumulation on the FP16 matrix cores.
+ *  * Calls that share a workspace must be ordered on one stream.
+ */
+#ifndef SB2_H
+#define SB2_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SB2_OK = 0,
+  SB2_EINVAL = -1,       /* null pointer, non-finite or non-positive dt, bad enum   */
+  SB2_ESHAPE = -2,       /* N or T out of range                                     */
+  SB2_EWORKSPACE = -3,   /* ws_bytes smaller than sb2_workspace_size(...)           */
+  SB2_EHIP = -4,         /* a HIP runtime call or kernel launch failed              */
+  SB2_EUNSUPPORTED = -5  /* precision not available for this entry point            */
+} sb2_status;
+
+typedef enum {
+  SB2_FP64 = 0,
+  SB2_FP32 = 1,
+  SB2_SPLIT_FP16 = 2
+} sb2_precision;
+
+/* Operation codes for sb2_workspace_size. */
+typedef enum {
+  SB2_OP_SIGMA = 0,
+  SB2_OP_COLLISION = 1,
+  SB2_OP_COLLISION_BACKWARD = 2,
+  SB2_OP_RHO_STEP = 3
+} sb2_op;
+
+/* Largest basis size and history length accepted. */
+#define SB2_MAX_N 128
+#define SB2_MAX_T 65536
+
+/* sb2_sigma -- second-Born self-energies for B pairs of times (Sec. III, Eq. 13).
+ *
+ *   Sigma_ij = sum_{mnpqrs} v_irpn (2 v_mqsj - v_qmsj) G_nm G_pq Gbar_sr,
+ *
+ * which is Eq. 13 with the exchange term's summation indices renamed; it holds
+ * for any real v.  For pair b, Gl[b] = G^<(t, t'_b) and Gg[b] = G^>(t, t'_b)
+ * (N x N complex each); the reversed-time functions are formed internally as
+ * Gbar = G(t', t) = -G(t, t')^dagger (Sec. II), and
+ *   Sl[b] = Sigma^<(t, t'_b) = Sigma(G = Gl[b], Gbar = -Gg[b]^dagger),
+ *   Sg[b] = Sigma^>(t, t'_b) = Sigma(G = Gg[b], Gbar = -Gl[b]^dagger).
+ * Outputs are B x N x N complex float64, overwritten.
+ * Errors: SB2_ESHAPE for N < 1, N > SB2_MAX_N or B < 1; SB2_EINVAL for null
+ * pointers or an unknown prec; SB2_EWORKSPACE.                                */
+int sb2_sigma(int N, int B, const double* v, const void* Gl, const void* Gg,
+              void* Sl, void* Sg, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* sb2_collision -- GKBA collision integral (Sec. II, Eqs. 9-11).
+ *
+ *   I(t) = dt * sum_{k=0}^{T-1} [ Sigma^>(t, t_k) G^<(t_k, t) - Sigma^<(t, t_k) G^>(t_k, t) ]
+ *
+ * the first two terms of Eq. 9 on the left-rectangle grid (the last two terms
+ * are the Hermitian conjugate of these, so Eq. 9's integral is I + I^dagger).
+ * Two-time functions come from the GKBA (Eq. 10) with the HF propagator of
+ * Eq. 11 for the frozen one-body matrix h: U_k = exp(-i h (T-k) dt),
+ *   G^<(t,t_k) = i U_k rho_k,      G^>(t,t_k) = -i U_k (1 - rho_k),
+ *   G^<(t_k,t) = i rho_k U_k^dag,  G^>(t_k,t) = -i (1 - rho_k) U_k^dag.
+ * h: N x N complex; rho_hist: T x N x N complex; I_out: N x N complex (overwritten).
+ * Sigma_out: optional (may be NULL) 2 x T x N x N complex receiving
+ *   Sigma_out[0][k] = Sigma^<(t, t_k), Sigma_out[1][k] = Sigma^>(t, t_k).
+ * Errors: SB2_ESHAPE (N, T out of range), SB2_EINVAL (null pointer, dt not
+ * finite or <= 0, unknown prec), SB2_EWORKSPACE.                              */
+int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
+                  void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* sb2_collision_backward -- adjoint of sb2_collision (FP64 only).
+ *
+ * Given gI = dL/dI for a real scalar L in torch's convention
+ * (gI = dL/dRe I + i dL/dIm I, N x N complex), writes
+ *   gv   = dL/dv          N^4 float64 (v treated as an unconstrained real tensor),
+ *   gh   = dL/dh          N x N complex (h treated as an unconstrained complex
+ *                         matrix; the propagators' dependence on h goes through
+ *                         the chain U_k = U_1^(T-k), U_1 = exp(-i h dt)),
+ *   grho = dL/drho_hist   T x N x N complex,
+ * all in the same convention and overwritten.  The GKBA functions and the
+ * contraction intermediates are recomputed, not stored.
+ * Errors: as sb2_collision; SB2_EUNSUPPORTED for prec != SB2_FP64.          */
+int sb2_collision_backward(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
+                           const void* gI, double* gv, void* gh, void* grho,
+                           int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* One system of a batched collision-integral evaluation. */
+typedef struct {
+  int N, T;
+  double dt;
+  const double* v;       /* N^4 float64            */
+  const void* h;         /* N x N complex          */
+  const void* rho_hist;  /* T x N x N complex      */
+  void* I_out;           /* N x N complex (out)    */
+} sb2_system;
+
+/* sb2_collision_batched -- sb2_collision for nsys independent systems of
+ * uneven N and T in one enqueue: every stage runs as one persistent launch
+ * over the work items of all systems (the descriptor array `sys` is read on
+ * the host; every pointer in it is a device pointer).  Results equal nsys
+ * calls of sb2_collision with the same prec up to the order of float32
+ * accumulation.  Errors: as sb2_collision for any system; SB2_EINVAL for
+ * nsys < 1 or sys == NULL.                                                   */
+int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, size_t ws_bytes,
+                          void* stream);
+size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec);
+
+/* sb2_rho_step -- one exponential-Euler step of Eq. 8 for rho = -i G^<(t,t):
+ *   rho_out = U rho U^dag - dt (I + I^dagger),  U = exp(-i h dt).
+ * h, rho, I: N x N complex; rho_out: N x N complex (may alias rho).           */
+int sb2_rho_step(int N, const void* h, const void* rho, const void* I, double dt, void* rho_out,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for op (an sb2_op) at basis size N, history length T
+ * (T = number of pairs B for SB2_OP_SIGMA, ignored for SB2_OP_RHO_STEP) and
+ * precision prec.  Returns 0 for invalid arguments.                         */
+size_t sb2_workspace_size(int op, int N, int T, int prec);
+
+/* Static description of a status code. */
+const char* sb2_status_string(int status);
+
+/* Stage timing for measurement (not for use under stream capture).
+ * sb2_profile_enable(1) makes later calls bracket each stage launch with HIP
+ * events recorded on the caller's stream; sb2_profile_read waits for those
+ * events and returns, per slot, the summed milliseconds and the number of
+ * launches since the last read or enable, then clears them.  Slots: 0..3 the
+ * four contractions R1..R4 of the self-energy chain, 4 the interaction
+ * layout, 5 propagators and GKBA functions, 6 operand packing and the split-K
+ * reduction, 7 the collision terms and the sum over past times.  The event
+ * objects are created lazily by the library and reused.                     */
+int sb2_profile_enable(int on);
+int sb2_profile_read(double* ms, int* launches, int nslots);
+
+/* Library version string. */
+const char* sb2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SB2_H */

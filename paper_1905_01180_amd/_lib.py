@@ -1,0 +1,214 @@
+"""ctypes binding of libsb2.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module checks tensor shapes,
+dtypes and devices, hands device pointers and the current HIP stream to the
+C ABI and keeps one reusable device workspace per device.  It fails loudly if
+the library is not built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsb2.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2}
+OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3}
+STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
+          -5: "SB2_EUNSUPPORTED"}
+
+_lib = None
+_lock = threading.Lock()
+
+_vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+
+
+class Sb2Error(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = lib().sb2_status_string(status).decode()
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [("N", _i), ("T", _i), ("dt", _d), ("v", _vp), ("h", _vp), ("rho_hist", _vp), ("I_out", _vp)]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsb2.so once; raise if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1905_01180_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.sb2_status_string.restype = ctypes.c_char_p
+        L.sb2_status_string.argtypes = [_i]
+        L.sb2_version.restype = ctypes.c_char_p
+        L.sb2_workspace_size.restype = _sz
+        L.sb2_workspace_size.argtypes = [_i, _i, _i, _i]
+        L.sb2_sigma.restype = _i
+        L.sb2_sigma.argtypes = [_i, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]
+        L.sb2_collision.restype = _i
+        L.sb2_collision.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
+        L.sb2_collision_backward.restype = _i
+        L.sb2_collision_backward.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _i, _vp, _sz, _vp]
+        L.sb2_collision_batched.restype = _i
+        L.sb2_collision_batched.argtypes = [_i, ctypes.POINTER(SystemDesc), _i, _vp, _sz, _vp]
+        L.sb2_batched_workspace_size.restype = _sz
+        L.sb2_batched_workspace_size.argtypes = [_i, ctypes.POINTER(SystemDesc), _i]
+        L.sb2_rho_step.restype = _i
+        L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
+        _lib = L
+        return L
+
+
+def header_functions():
+    """Names of the functions declared in include/sb2.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(sb2_\w+)\s*\(", txt, re.M)))
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, int):
+        return prec
+    if prec not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {prec!r}")
+    return PRECISIONS[prec]
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+_ws = {}
+
+
+def workspace(nbytes: int, dev: torch.device) -> torch.Tensor:
+    """A cached device buffer of at least nbytes (grown, never shrunk)."""
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws.pop(key, None)
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        _ws[key] = buf
+    return buf
+
+
+def release_workspace():
+    _ws.clear()
+
+
+def _check(t: torch.Tensor, name: str, dtype, shape):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _call(fn: str, *args):
+    st = getattr(lib(), fn)(*args)
+    if st != 0:
+        raise Sb2Error(fn, st)
+
+
+def sb2_workspace_size(op: str, n: int, t: int, prec="fp64") -> int:
+    return int(lib().sb2_workspace_size(OPS[op] if isinstance(op, str) else op, n, t, _prec(prec)))
+
+
+def sb2_sigma(v: torch.Tensor, g_less: torch.Tensor, g_great: torch.Tensor, prec="fp64"):
+    """Sigma^<, Sigma^> (B, N, N) complex128 for B pairs G^<(t,t'_b), G^>(t,t'_b)."""
+    b, n = g_less.shape[0], g_less.shape[1]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(g_less, "g_less", torch.complex128, (b, n, n))
+    _check(g_great, "g_great", torch.complex128, (b, n, n))
+    p = _prec(prec)
+    nbytes = sb2_workspace_size("sigma", n, b, p)
+    ws = workspace(nbytes, v.device)
+    s_less = torch.empty_like(g_less)
+    s_great = torch.empty_like(g_great)
+    _call("sb2_sigma", n, b, v.data_ptr(), g_less.data_ptr(), g_great.data_ptr(), s_less.data_ptr(),
+          s_great.data_ptr(), p, ws.data_ptr(), ws.numel(), _stream(v.device))
+    return s_less, s_great
+
+
+def sb2_collision(v: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: float, prec="fp64",
+                  return_sigma: bool = False):
+    """I_ns(t) (N, N) complex128; with return_sigma also Sigma (2, T, N, N)."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    p = _prec(prec)
+    ws = workspace(sb2_workspace_size("collision", n, t, p), v.device)
+    out = torch.empty((n, n), dtype=torch.complex128, device=v.device)
+    sig = torch.empty((2, t, n, n), dtype=torch.complex128, device=v.device) if return_sigma else None
+    _call("sb2_collision", n, t, v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt), out.data_ptr(),
+          sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(), _stream(v.device))
+    return (out, sig) if return_sigma else out
+
+
+def sb2_collision_backward(v, h, rho_hist, dt, grad_i, prec="fp64"):
+    """(dL/dv, dL/dh, dL/drho_hist) for the cotangent grad_i = dL/dI (torch convention)."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    _check(grad_i, "grad_i", torch.complex128, (n, n))
+    p = _prec(prec)
+    ws = workspace(sb2_workspace_size("collision_backward", n, t, p), v.device)
+    gv = torch.empty_like(v)
+    gh = torch.empty_like(h)
+    gr = torch.empty_like(rho_hist)
+    _call("sb2_collision_backward", n, t, v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt),
+          grad_i.data_ptr(), gv.data_ptr(), gh.data_ptr(), gr.data_ptr(), p, ws.data_ptr(), ws.numel(),
+          _stream(v.device))
+    return gv, gh, gr
+
+
+def sb2_rho_step(h, rho, i_ns, dt):
+    """rho(t+dt) = U rho U^dag - dt (I + I^dag), U = exp(-i h dt)."""
+    n = h.shape[0]
+    for name, x in (("h", h), ("rho", rho), ("i_ns", i_ns)):
+        _check(x, name, torch.complex128, (n, n))
+    ws = workspace(sb2_workspace_size("rho_step", n, 1, 0), h.device)
+    out = torch.empty_like(rho)
+    _call("sb2_rho_step", n, h.data_ptr(), rho.data_ptr(), i_ns.data_ptr(), float(dt), out.data_ptr(),
+          ws.data_ptr(), ws.numel(), _stream(h.device))
+    return out
+
+
+def _descs(systems, outs):
+    arr = (SystemDesc * len(systems))()
+    for d, (v, h, rho, dt), o in zip(arr, systems, outs):
+        n, t = h.shape[0], rho.shape[0]
+        _check(v, "v", torch.float64, (n, n, n, n))
+        _check(h, "h", torch.complex128, (n, n))
+        _check(rho, "rho_hist", torch.complex128, (t, n, n))
+        d.N, d.T, d.dt = n, t, float(dt)
+        d.v, d.h, d.rho_hist, d.I_out = v.data_ptr(), h.data_ptr(), rho.data_ptr(), o.data_ptr()
+    return arr
+
+
+def sb2_collision_batched(systems, prec="fp16x3"):
+    """I_ns for a list of (v, h, rho_hist, dt) systems in one enqueue."""
+    outs = [torch.empty((h.shape[0], h.shape[0]), dtype=torch.complex128, device=h.device)
+            for (_, h, _, _) in systems]
+    arr = _descs(systems, outs)
+    p = _prec(prec)
+    dev = systems[0][1].device
+    nbytes = int(lib().sb2_batched_workspace_size(len(systems), arr, p))
+    ws = workspace(nbytes, dev)
+    _call("sb2_collision_batched", len(systems), arr, p, ws.data_ptr(), ws.numel(), _stream(dev))
+    return outs

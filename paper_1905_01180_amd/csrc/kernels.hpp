@@ -1,0 +1,338 @@
+// Small kernels of the GKBA collision-integral path: matrix exponential,
+// GKBA two-time slices, layout preparation of the interaction tensor, packing
+// of the per-chunk operands, reductions.  The bulk contractions live in gemm.hpp.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gemm.hpp"
+
+namespace sb2 {
+
+typedef double cplx __attribute__((ext_vector_type(2)));   // (re, im)
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  cplx r;
+  r[0] = a[0] * b[0] - a[1] * b[1];
+  r[1] = a[0] * b[1] + a[1] * b[0];
+  return r;
+}
+__device__ __forceinline__ cplx mk(double re, double im) {
+  cplx r;
+  r[0] = re;
+  r[1] = im;
+  return r;
+}
+__device__ __forceinline__ cplx conj_(cplx a) { return mk(a[0], -a[1]); }
+__device__ __forceinline__ cplx times_i(cplx a) { return mk(-a[1], a[0]); }       // i a
+__device__ __forceinline__ cplx times_mi(cplx a) { return mk(a[1], -a[0]); }      // -i a
+
+__global__ void k_fill_u32(unsigned* p, int n, unsigned val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+// Block-wide max, then one atomic per block.
+__device__ __forceinline__ void block_atomic_max(float x, unsigned* dst) {
+  __shared__ float red[16];
+  x = wave_max(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = 0.f;
+    for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) m = fmaxf(m, red[i]);
+    if (m > 0.f) atomicMax(dst, __float_as_uint(m));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix exponential E = exp(alpha H) of one N x N complex matrix (N <= 128),
+// one workgroup of 1024 threads.  Scaling and squaring with a Taylor polynomial
+// (Moler & Van Loan, "Nineteen dubious ways to compute the exponential of a
+// matrix", method 3): X = alpha H / 2^s with ||X||_1 <= 1/2, E = sum_{j<=16}
+// X^j / j! by Horner's rule, then s squarings.  Truncation error of the series
+// is below ||X||^17 / 17! < 1e-20.  Matrices live in global scratch (L2
+// resident); each product stages 16-wide K slabs of both factors in LDS.
+// ---------------------------------------------------------------------------
+constexpr int EXPM_THREADS = 1024;
+constexpr int EXPM_MAXN = 128;
+
+// C = A B (+ I if add_eye) scaled by `scale`; all N x N row-major complex.
+__device__ void wg_matmul(int N, const cplx* __restrict__ A, const cplx* __restrict__ B, cplx* __restrict__ C,
+                          double scale, bool add_eye) {
+  __shared__ cplx sa[EXPM_MAXN][17];
+  __shared__ cplx sb[16][EXPM_MAXN + 1];
+  const int t = threadIdx.x;
+  const int ti = t >> 5, tj = t & 31;        // rows ti + 32a, cols tj + 32b
+  cplx acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0, 0);
+  for (int k0 = 0; k0 < N; k0 += 16) {
+    __syncthreads();
+    for (int e = t; e < EXPM_MAXN * 16; e += EXPM_THREADS) {
+      const int r = e >> 4, c = e & 15;
+      sa[r][c] = (r < N && k0 + c < N) ? A[r * N + k0 + c] : mk(0, 0);
+      const int rb = e / EXPM_MAXN, cb = e % EXPM_MAXN;
+      sb[rb][cb] = (k0 + rb < N && cb < N) ? B[(k0 + rb) * N + cb] : mk(0, 0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      cplx av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sa[ti + 32 * a][kk];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = sb[kk][tj + 32 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b][0] = fma(av[a][0], bv[b][0], fma(-av[a][1], bv[b][1], acc[a][b][0]));
+          acc[a][b][1] = fma(av[a][0], bv[b][1], fma(av[a][1], bv[b][0], acc[a][b][1]));
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + 32 * a, j = tj + 32 * b;
+      if (i < N && j < N) {
+        cplx r = acc[a][b] * scale;
+        if (add_eye && i == j) r[0] += 1.0;
+        C[i * N + j] = r;
+      }
+    }
+  __syncthreads();
+}
+
+// E = exp(alpha H); scratch: 2 N^2 complex.
+__global__ void __launch_bounds__(EXPM_THREADS)
+k_expm(int N, const cplx* __restrict__ H, double alpha_re, double alpha_im, cplx* __restrict__ E,
+       cplx* __restrict__ X, cplx* __restrict__ S) {
+  __shared__ double colsum[EXPM_MAXN];
+  __shared__ int s_sh;
+  const int t = threadIdx.x;
+  const cplx alpha = mk(alpha_re, alpha_im);
+  for (int e = t; e < N * N; e += EXPM_THREADS) X[e] = cmul(alpha, H[e]);
+  __syncthreads();
+  // ||X||_1 = max_j sum_i |X_ij|
+  for (int j = t; j < N; j += EXPM_THREADS) {
+    double s = 0;
+    for (int i = 0; i < N; ++i) {
+      const cplx x = X[i * N + j];
+      s += sqrt(x[0] * x[0] + x[1] * x[1]);
+    }
+    colsum[j] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double nrm = 0;
+    for (int j = 0; j < N; ++j) nrm = fmax(nrm, colsum[j]);
+    int s = 0;
+    while (nrm > 0.5 && s < 1000) { nrm *= 0.5; ++s; }
+    s_sh = s;
+  }
+  __syncthreads();
+  const int s = s_sh;
+  const double sc = ldexp(1.0, -s);
+  for (int e = t; e < N * N; e += EXPM_THREADS) {
+    X[e] = X[e] * sc;
+    const int i = e / N, j = e - (e / N) * N;
+    E[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  // Horner: E <- I + X E / j, j = 16..1
+  for (int j = 16; j >= 1; --j) {
+    wg_matmul(N, X, E, S, 1.0 / j, true);
+    for (int e = t; e < N * N; e += EXPM_THREADS) E[e] = S[e];
+    __syncthreads();
+  }
+  for (int q = 0; q < s; ++q) {
+    wg_matmul(N, E, E, S, 1.0, false);
+    for (int e = t; e < N * N; e += EXPM_THREADS) E[e] = S[e];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GKBA two-time slices from U_k, X_k = U_k rho_k and Y_k = rho_k U_k^dag:
+//   G^<(t,t_k) = i X_k,  G^>(t,t_k) = -i (U_k - X_k),
+//   G^<(t_k,t) = i Y_k,  G^>(t_k,t) = -i (U_k^dag - Y_k).
+// ---------------------------------------------------------------------------
+__global__ void k_gkba(int N, int T, const cplx* __restrict__ U, const cplx* __restrict__ X,
+                       const cplx* __restrict__ Y, cplx* __restrict__ Gl, cplx* __restrict__ Gg,
+                       cplx* __restrict__ Glb, cplx* __restrict__ Ggb) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  const i64 nn = (i64)N * N;
+  if (e >= nn * T) return;
+  const i64 k = e / nn;
+  const int r = (int)(e - k * nn);
+  const int i = r / N, j = r - (r / N) * N;
+  const cplx u = U[e], x = X[e], y = Y[e];
+  const cplx ud = conj_(U[k * nn + (i64)j * N + i]);
+  Gl[e] = times_i(x);
+  Gg[e] = times_mi(u - x);
+  Glb[e] = times_i(y);
+  Ggb[e] = times_mi(ud - y);
+}
+
+// ---------------------------------------------------------------------------
+// Per-chunk operand packing.  Slice b = 2 (k - k0) + sigma holds
+//   sigma = 0:  G = G^<(t,t_k), Gbar = G^>(t_k,t)   (-> Sigma^<)
+//   sigma = 1:  G = G^>(t,t_k), Gbar = G^<(t_k,t)   (-> Sigma^>)
+// cast to the bulk precision T.  When gbar_from_g is set, Gbar is formed as
+// -G'^dag from the opposite-kind function (Gl, Gg are then per-pair inputs).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cplx* __restrict__ Gg,
+                       const cplx* __restrict__ Glb, const cplx* __restrict__ Ggb, int gbar_from_g,
+                       T* __restrict__ Gs, T* __restrict__ Gbs, unsigned* gmax, unsigned* gbmax) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  float mg = 0.f, mb = 0.f;
+  if (e < 2 * nn * npairs) {
+    const i64 b = e / nn;
+    const int r = (int)(e - b * nn);
+    const int i = r / N, j = r - (r / N) * N;
+    const i64 kp = b >> 1;
+    const int sig = (int)(b & 1);
+    const cplx g = sig == 0 ? Gl[kp * nn + r] : Gg[kp * nn + r];
+    cplx gb;
+    if (gbar_from_g) {
+      const cplx o = sig == 0 ? Gg[kp * nn + (i64)j * N + i] : Gl[kp * nn + (i64)j * N + i];
+      gb = mk(-o[0], o[1]);                     // -conj(o_ji)
+    } else {
+      gb = sig == 0 ? Ggb[kp * nn + r] : Glb[kp * nn + r];
+    }
+    Gs[2 * e] = (T)g[0];
+    Gs[2 * e + 1] = (T)g[1];
+    Gbs[2 * e] = (T)gb[0];
+    Gbs[2 * e + 1] = (T)gb[1];
+    mg = fmaxf(fabsf((float)g[0]), fabsf((float)g[1]));
+    mb = fmaxf(fabsf((float)gb[0]), fabsf((float)gb[1]));
+  }
+  if (gmax) {
+    block_atomic_max(mg, gmax);
+    __syncthreads();
+    block_atomic_max(mb, gbmax);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interaction layouts for the contraction chain (one workgroup per N x N
+// block, transposed through LDS):
+//   W[m][q][j][s]  = 2 v_mqsj - v_qmsj     (right-hand vertex, exchange folded in)
+//   Vp[i][n][p][r] = v_irpn                (left-hand vertex, contraction index (n,p,r))
+// ---------------------------------------------------------------------------
+// 32 x 32 LDS-tiled transpose of one N x N block: out[c][r] = f(in[r][c]).
+template <typename T>
+__device__ __forceinline__ float transpose_block(int N, const double* __restrict__ a, i64 sar,
+                                                 const double* __restrict__ b, i64 sbr, double cb,
+                                                 T* __restrict__ out, i64 sor) {
+  __shared__ T tile[32][33];
+  float mx = 0.f;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 256 threads: 32 x 8
+  for (int r0 = 0; r0 < N; r0 += 32)
+    for (int c0 = 0; c0 < N; c0 += 32) {
+      __syncthreads();
+      for (int yy = ty; yy < 32; yy += 8) {
+        const int r = r0 + yy, c = c0 + tx;
+        if (r < N && c < N) {
+          double x = a[r * sar + c];
+          if (b) x = 2.0 * x - cb * b[r * sbr + c];
+          tile[yy][tx] = (T)x;
+          mx = fmaxf(mx, fabsf((float)x));
+        }
+      }
+      __syncthreads();
+      for (int yy = ty; yy < 32; yy += 8) {
+        const int c = c0 + yy, r = r0 + tx;
+        if (r < N && c < N) out[c * sor + r] = tile[tx][yy];
+      }
+    }
+  return mx;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep_w(int N, const double* __restrict__ v, T* __restrict__ W,
+                                                unsigned* wmax) {
+  const int m = blockIdx.x / N, q = blockIdx.x % N;
+  const i64 nn = (i64)N * N;
+  // rows s, cols j of v[m][q][s][j] and v[q][m][s][j]; out rows j, cols s of W[m][q][j][s]
+  const float mx = transpose_block<T>(N, v + ((i64)m * N + q) * nn, N, v + ((i64)q * N + m) * nn, N, 1.0,
+                                      W + ((i64)m * N + q) * nn, N);
+  if (wmax) block_atomic_max(mx, wmax);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep_vp(int N, const double* __restrict__ v, T* __restrict__ Vp,
+                                                 unsigned* vmax) {
+  const int i = blockIdx.x / N, p = blockIdx.x % N;
+  const i64 nn = (i64)N * N;
+  // rows r (stride N^2), cols n of v[i][r][p][n]; out rows n (stride N^2), cols r of Vp[i][n][p][r]
+  const float mx = transpose_block<T>(N, v + (i64)i * N * nn + (i64)p * N, nn, nullptr, 0, 0.0,
+                                      Vp + (i64)i * N * nn + (i64)p * N, nn);
+  if (vmax) block_atomic_max(mx, vmax);
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reduction of the last contraction: part[z][i][c], c = b N + j over
+// the chunk's slices, summed over z in order (float64) into
+//   S_less[k][i][j] (b even) / S_great[k][i][j] (b odd), k = k0 + b/2,
+// and optionally copied into a second destination of the same layout.
+// ---------------------------------------------------------------------------
+__global__ void k_reduce_sigma(int N, int nslices, int nz, const cplx* __restrict__ part, i64 kbase,
+                               cplx* __restrict__ S_less, cplx* __restrict__ S_great,
+                               cplx* __restrict__ O_less, cplx* __restrict__ O_great) {
+  const i64 ncol = (i64)nslices * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncol * N) return;
+  const int i = (int)(e / ncol);
+  const i64 c = e - (i64)i * ncol;
+  const i64 b = c / N;
+  const int j = (int)(c - b * N);
+  cplx acc = mk(0, 0);
+  for (int z = 0; z < nz; ++z) acc += part[(i64)z * N * ncol + e];
+  const i64 k = kbase + (b >> 1);
+  const i64 o = k * N * N + (i64)i * N + j;
+  if (b & 1) {
+    S_great[o] = acc;
+    if (O_great) O_great[o] = acc;
+  } else {
+    S_less[o] = acc;
+    if (O_less) O_less[o] = acc;
+  }
+}
+
+// I = dt sum_k terms[k], the k-sum in k order in float64.
+__global__ void k_sum_terms(int N, int T, const cplx* __restrict__ terms, double dt, cplx* __restrict__ I) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const i64 nn = (i64)N * N;
+  if (e >= nn) return;
+  cplx acc = mk(0, 0);
+  for (int k = 0; k < T; ++k) acc += terms[k * nn + e];
+  I[e] = acc * dt;
+}
+
+// rho_out = Y - dt (I + I^dag)
+__global__ void k_rho_finish(int N, const cplx* __restrict__ Y, const cplx* __restrict__ I, double dt,
+                             cplx* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int i = e / N, j = e - (e / N) * N;
+  const cplx a = I[e], b = conj_(I[j * N + i]);
+  out[e] = Y[e] - (a + b) * dt;
+}
+
+// Strided complex copy, used to lay out small operands.
+__global__ void k_copy(i64 n, const cplx* __restrict__ src, cplx* __restrict__ dst) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+
+}  // namespace sb2

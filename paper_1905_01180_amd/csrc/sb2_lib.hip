@@ -1,0 +1,589 @@
+// libsb2: C ABI of the second-Born self-energy / GKBA collision-integral path.
+//
+// Contraction chain (Eq. 13 regrouped; Eq. 19 / Fig. 2 give the paper's own
+// path, this is another valid one).  With w_mqsj = 2 v_mqsj - v_qmsj,
+//   Sigma_ij = sum v_irpn w_mqsj G_nm G_pq Gbar_sr
+// is evaluated per slice (pair of times, kind <>) as four GEMMs whose big
+// operand is always contiguous:
+//   R1  A[n][q][j][s] = sum_m G_nm W[m][q][j][s]            (slices stacked: M = 2S N)
+//   R2  B[n][p][j][s] = sum_q G_pq A[n][q][j][s]            (batched over (slice, n))
+//   R3  C[j][n][p][r] = sum_s B[n][p][j][s] Gbar_sr         (batched over slices)
+//   R4  Sigma_ij      = sum_{(n,p,r)} Vp[i][n][p][r] C[j][n][p][r]   (split-K, float64 partials)
+// with the interaction laid out once per call as W[m][q][j][s] = w_mqsj and
+// Vp[i][n][p][r] = v_irpn.  R1 and R4 share W / Vp across all slices of a chunk
+// of past times; the intermediates A/C and B each take 2S N^4 complex entries.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+#include "sb2.h"
+
+using namespace sb2;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+constexpr size_t C128 = 16;                       // bytes of one complex float64
+constexpr size_t INTERMEDIATE_BUDGET = 32ull << 30;  // bytes for the two chain intermediates
+
+enum ScaleWord { S_GMAX = 0, S_GBMAX, S_WMAX, S_VMAX, S_AMAX, S_BMAX, S_CMAX, S_NWORDS };
+
+inline bool prec_ok(int p) { return p == SB2_FP64 || p == SB2_FP32 || p == SB2_SPLIT_FP16; }
+inline size_t bulk_bytes(int p) { return p == SB2_FP64 ? 8 : 4; }   // one real scalar of the bulk type
+
+GemmArgs gdef() {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nbl = 1;
+  g.alpha_re = 1.0;
+  g.kpromote = 4;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM launchers
+// ---------------------------------------------------------------------------
+template <typename T, typename OutT, int WM, int WN, int FM, int FN, bool AC, bool BC, bool ACC64>
+hipError_t launch_f(GemmArgs g, int nbatch, hipStream_t s) {
+  constexpr int BM = 16 * FM * WM, BN = 16 * FN * WN;
+  if (g.kchunk <= 0) g.kchunk = g.K > 0 ? g.K : 1;
+  g.tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int nz = g.K > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
+  dim3 grid(g.tiles_m * tiles_n, nbatch, nz);
+  hipLaunchKernelGGL((k_gemm<T, OutT, WM, WN, FM, FN, AC, BC, ACC64>), grid, dim3(64 * WM * WN), 0, s, g);
+  return hipGetLastError();
+}
+
+template <typename OutT, int WM, int WN, int FM, int FN, bool AC, bool BC, bool ACC64>
+hipError_t launch_h(GemmArgs g, int nbatch, hipStream_t s) {
+  constexpr int BM = 16 * FM * WM, BN = 16 * FN * WN;
+  if (g.kchunk <= 0) g.kchunk = g.K > 0 ? g.K : 1;
+  g.tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int nz = g.K > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
+  dim3 grid(g.tiles_m * tiles_n, nbatch, nz);
+  hipLaunchKernelGGL((k_gemm_h16<OutT, WM, WN, FM, FN, AC, BC, ACC64>), grid, dim3(64 * WM * WN), 0, s, g);
+  return hipGetLastError();
+}
+
+// float64 complex x complex, small-M shape (N x N products, propagators, collision terms)
+hipError_t zgemm(GemmArgs g, int nbatch, hipStream_t s) {
+  return launch_f<double, double, 1, 4, 7, 1, true, true, false>(g, nbatch, s);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace plans
+// ---------------------------------------------------------------------------
+struct ChainPlan {
+  int N = 0, S = 0, nz = 1, kchunk = 1;
+  size_t w = 0, vp = 0, gs = 0, gbs = 0, x1 = 0, x2 = 0, part = 0, scal = 0, end = 0;
+};
+
+// R4 split-K: enough workgroups to fill the chip, chunk a multiple of the slab depth.
+void r4_split(int N, int ns, int prec, int& nz, int& kchunk) {
+  const long long K = (long long)N * N * N;
+  const int bk = prec == SB2_SPLIT_FP16 ? 32 : 16;
+  const long long coltiles = ((long long)ns * N + 63) / 64;
+  const long long rowtiles = (N + 111) / 112;
+  long long want = (2048 + coltiles * rowtiles - 1) / (coltiles * rowtiles);
+  const long long maxz = (K + bk - 1) / bk;
+  if (want < 1) want = 1;
+  if (want > maxz) want = maxz;
+  if (want > 4096) want = 4096;
+  long long kc = (K + want - 1) / want;
+  kc = (kc + bk - 1) / bk * bk;
+  kchunk = (int)kc;
+  nz = (int)((K + kc - 1) / kc);
+}
+
+ChainPlan chain_plan(int N, int pairs, int prec, size_t base) {
+  ChainPlan p;
+  p.N = N;
+  const size_t n4 = (size_t)N * N * N * N, n2 = (size_t)N * N;
+  const size_t bb = bulk_bytes(prec);
+  const size_t per_pair = 2 * 2 * n4 * 2 * bb;      // two buffers x two slices x N^4 complex
+  size_t S = INTERMEDIATE_BUDGET / per_pair;
+  if (S < 1) S = 1;
+  if (S > (size_t)pairs) S = pairs;
+  const size_t smax = 65535 / (2 * (size_t)N);       // R2 batch = 2 S N launches in grid.y
+  if (S > smax) S = smax;
+  p.S = (int)S;
+  r4_split(N, 2 * p.S, prec, p.nz, p.kchunk);
+  size_t o = base;
+  p.scal = o; o += al(S_NWORDS * 4);
+  p.w = o; o += al(n4 * bb);
+  p.vp = o; o += al(n4 * bb);
+  p.gs = o; o += al(2 * S * n2 * 2 * bb);
+  p.gbs = o; o += al(2 * S * n2 * 2 * bb);
+  p.x1 = o; o += al(2 * S * n4 * 2 * bb);
+  p.x2 = o; o += al(2 * S * n4 * 2 * bb);
+  p.part = o; o += al((size_t)p.nz * N * 2 * S * N * C128);
+  p.end = o;
+  return p;
+}
+
+struct CollPlan {
+  size_t U, X, Y, Gl, Gg, Glb, Ggb, Sl, Sg, terms, ex1, ex2;
+  ChainPlan ch;
+  size_t end;
+};
+
+CollPlan coll_plan(int N, int T, int prec) {
+  CollPlan c;
+  const size_t hist = (size_t)T * N * N * C128;
+  size_t o = 0;
+  c.U = o; o += al(hist);
+  c.X = o; o += al(hist);
+  c.Y = o; o += al(hist);
+  c.Gl = o; o += al(hist);
+  c.Gg = o; o += al(hist);
+  c.Glb = o; o += al(hist);
+  c.Ggb = o; o += al(hist);
+  c.Sl = o; o += al(hist);
+  c.Sg = o; o += al(hist);
+  c.terms = o; o += al(hist);
+  c.ex1 = o; o += al((size_t)N * N * C128);
+  c.ex2 = o; o += al((size_t)N * N * C128);
+  c.ch = chain_plan(N, T, prec, o);
+  c.end = c.ch.end;
+  return c;
+}
+
+size_t rho_plan(int N) { return 4 * al((size_t)N * N * C128); }
+
+inline char* at(void* ws, size_t off) { return reinterpret_cast<char*>(ws) + off; }
+
+// ---------------------------------------------------------------------------
+// Optional stage timing with HIP events recorded on the launch stream (off by
+// default; used by the benchmark).  Slots: 0..3 = R1..R4, 4 = interaction
+// layout, 5 = propagators + GKBA, 6 = operand packing + split-K reduction,
+// 7 = collision terms + sum over past times.
+// ---------------------------------------------------------------------------
+constexpr int NSLOTS = 8;
+struct ProfRec { int slot; hipEvent_t a, b; };
+struct Prof {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+Prof g_prof;
+
+struct StageTimer {
+  hipEvent_t b_ = nullptr;
+  hipStream_t s_;
+  int slot_;
+  hipEvent_t a_ = nullptr;
+  StageTimer(int slot, hipStream_t s) : s_(s), slot_(slot) {
+    if (!g_prof.on) return;
+    a_ = g_prof.get();
+    b_ = g_prof.get();
+    if (a_ && b_) (void)hipEventRecord(a_, s_);
+  }
+  ~StageTimer() {
+    if (!g_prof.on || !a_ || !b_) return;
+    (void)hipEventRecord(b_, s_);
+    g_prof.recs.push_back({slot_, a_, b_});
+  }
+};
+
+#define SB2_TRY(expr)                      \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return SB2_EHIP; \
+  } while (0)
+
+inline int blocks(long long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// ---------------------------------------------------------------------------
+// The chain for one chunk of ns slices
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t prep_interaction(int N, const double* v, const ChainPlan& p, void* ws, int prec, hipStream_t s) {
+  unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scal, (int)S_NWORDS, 0u);
+  const bool h = prec == SB2_SPLIT_FP16;
+  hipLaunchKernelGGL(k_prep_w<T>, dim3(N * N), dim3(256), 0, s, N, v, reinterpret_cast<T*>(at(ws, p.w)),
+                     h ? scal + S_WMAX : nullptr);
+  hipLaunchKernelGGL(k_prep_vp<T>, dim3(N * N), dim3(256), 0, s, N, v, reinterpret_cast<T*>(at(ws, p.vp)),
+                     h ? scal + S_VMAX : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipStream_t st) {
+  const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
+  const void* Gs = at(ws, p.gs);
+  const void* Gbs = at(ws, p.gbs);
+  const void* W = at(ws, p.w);
+  const void* Vp = at(ws, p.vp);
+  void* X1 = at(ws, p.x1);
+  void* X2 = at(ws, p.x2);
+  void* part = at(ws, p.part);
+  const bool h16 = prec == SB2_SPLIT_FP16;
+  hipError_t e;
+
+  // R1: A[(b,n)][(q,j,s)] = sum_m G[(b,n)][m] W[m][(q,j,s)]
+  GemmArgs g = gdef();
+  g.M = ns * N; g.N = (int)n3; g.K = N;
+  g.A = Gs; g.sAm = N; g.sAk = 1;
+  g.B = W; g.sBk = n3; g.sBn = 1;
+  g.C = X1; g.sCm = n3; g.sCn = 1;
+  if (h16) { g.amax = scal + S_GMAX; g.bmax = scal + S_WMAX; g.cmax = scal + S_AMAX; }
+  {
+    StageTimer tm(0, st);
+    if (prec == SB2_FP64) e = launch_f<double, double, 2, 2, 2, 2, true, false, false>(g, 1, st);
+    else if (prec == SB2_FP32) e = launch_f<float, float, 2, 2, 4, 4, true, false, false>(g, 1, st);
+    else e = launch_h<float, 2, 2, 4, 4, true, false, false>(g, 1, st);
+  }
+  if (e != hipSuccess) return e;
+
+  // R2: B[b][n][p][(j,s)] = sum_q G_b[p][q] A[b][n][q][(j,s)], batch (b, n)
+  g = gdef();
+  g.M = N; g.N = (int)n2; g.K = N; g.nbl = N;
+  g.A = Gs; g.sAm = N; g.sAk = 1; g.sAbh = n2; g.sAbl = 0;
+  g.B = X1; g.sBk = n2; g.sBn = 1; g.sBbh = n4; g.sBbl = n3;
+  g.C = X2; g.sCm = n2; g.sCn = 1; g.sCbh = n4; g.sCbl = n3;
+  if (h16) { g.amax = scal + S_GMAX; g.bmax = scal + S_AMAX; g.cmax = scal + S_BMAX; }
+  {
+    StageTimer tm(1, st);
+    if (prec == SB2_FP64) e = launch_f<double, double, 1, 4, 7, 1, true, true, false>(g, ns * N, st);
+    else if (prec == SB2_FP32) e = launch_f<float, float, 1, 4, 7, 1, true, true, false>(g, ns * N, st);
+    else e = launch_h<float, 1, 4, 7, 1, true, true, false>(g, ns * N, st);
+  }
+  if (e != hipSuccess) return e;
+
+  // R3: C[b][j][n][p][r] = sum_s B[b][(n,p,j)][s] Gbar_b[s][r], batch b
+  g = gdef();
+  g.M = (int)n3; g.N = N; g.K = N;
+  g.A = X2; g.sAm = N; g.sAk = 1; g.sAbh = n4;
+  g.B = Gbs; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+  g.C = X1; g.Mlo = N; g.sCmh = N; g.sCm = n3; g.sCn = 1; g.sCbh = n4;
+  if (h16) { g.amax = scal + S_BMAX; g.bmax = scal + S_GBMAX; g.cmax = scal + S_CMAX; }
+  {
+    StageTimer tm(2, st);
+    if (prec == SB2_FP64) e = launch_f<double, double, 4, 1, 1, 7, true, true, false>(g, ns, st);
+    else if (prec == SB2_FP32) e = launch_f<float, float, 4, 1, 1, 7, true, true, false>(g, ns, st);
+    else e = launch_h<float, 4, 1, 1, 7, true, true, false>(g, ns, st);
+  }
+  if (e != hipSuccess) return e;
+
+  // R4: part[z][i][c] = sum_{k in chunk z} Vp[i][k] C[c][k], c = b N + j, k = (n,p,r)
+  g = gdef();
+  g.M = N; g.N = ns * N; g.K = (int)n3; g.kchunk = p.kchunk;
+  g.A = Vp; g.sAm = n3; g.sAk = 1;
+  g.B = X1; g.sBk = 1; g.sBn = n3;
+  g.C = part; g.sCm = (i64)ns * N; g.sCn = 1; g.sCz = (i64)N * ns * N;
+  if (h16) { g.amax = scal + S_VMAX; g.bmax = scal + S_CMAX; g.kpromote = 2; }
+  {
+    StageTimer tm(3, st);
+    if (prec == SB2_FP64) e = launch_f<double, double, 1, 4, 7, 1, false, true, false>(g, 1, st);
+    else if (prec == SB2_FP32) e = launch_f<float, double, 1, 4, 7, 1, false, true, true>(g, 1, st);
+    else e = launch_h<double, 1, 4, 7, 1, false, true, true>(g, 1, st);
+  }
+  return e;
+}
+
+template <typename T>
+hipError_t pack(int N, int npairs, const void* Gl, const void* Gg, const void* Glb, const void* Ggb,
+                int from_g, const ChainPlan& p, void* ws, bool h16, hipStream_t s) {
+  unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
+  if (h16) {
+    // the chain's per-chunk maxima start from zero (a fill kernel, so the
+    // sequence stays valid under stream capture)
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scal, 2, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scal + S_AMAX, 3, 0u);
+  }
+  const long long n = 2LL * N * N * npairs;
+  hipLaunchKernelGGL(k_pack<T>, dim3(blocks(n, 256)), dim3(256), 0, s, N, npairs,
+                     reinterpret_cast<const cplx*>(Gl), reinterpret_cast<const cplx*>(Gg),
+                     reinterpret_cast<const cplx*>(Glb), reinterpret_cast<const cplx*>(Ggb), from_g,
+                     reinterpret_cast<T*>(at(ws, p.gs)), reinterpret_cast<T*>(at(ws, p.gbs)),
+                     h16 ? scal + S_GMAX : nullptr, h16 ? scal + S_GBMAX : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t prep_dispatch(int prec, int N, const double* v, const ChainPlan& p, void* ws, hipStream_t s) {
+  StageTimer tm(4, s);
+  if (prec == SB2_FP64) return prep_interaction<double>(N, v, p, ws, prec, s);
+  return prep_interaction<float>(N, v, p, ws, prec, s);
+}
+
+hipError_t pack_dispatch(int prec, int N, int np, const void* Gl, const void* Gg, const void* Glb,
+                         const void* Ggb, int from_g, const ChainPlan& p, void* ws, hipStream_t s) {
+  StageTimer tm(6, s);
+  if (prec == SB2_FP64) return pack<double>(N, np, Gl, Gg, Glb, Ggb, from_g, p, ws, false, s);
+  return pack<float>(N, np, Gl, Gg, Glb, Ggb, from_g, p, ws, prec == SB2_SPLIT_FP16, s);
+}
+
+// Self-energies of `pairs` pairs (Gl[k], Gg[k]) -> S_less[k], S_great[k].
+hipError_t sigma_pairs(int prec, int N, int pairs, const double* v, const void* Gl, const void* Gg,
+                       const void* Glb, const void* Ggb, int from_g, cplx* S_less, cplx* S_great,
+                       cplx* O_less, cplx* O_great, const ChainPlan& p, void* ws, hipStream_t s) {
+  const size_t nn = (size_t)N * N;
+  hipError_t e = prep_dispatch(prec, N, v, p, ws, s);
+  if (e != hipSuccess) return e;
+  for (int k0 = 0; k0 < pairs; k0 += p.S) {
+    const int np = pairs - k0 < p.S ? pairs - k0 : p.S;
+    const size_t o = (size_t)k0 * nn * C128;
+    e = pack_dispatch(prec, N, np, (const char*)Gl + o, (const char*)Gg + o,
+                      Glb ? (const char*)Glb + o : nullptr, Ggb ? (const char*)Ggb + o : nullptr, from_g, p,
+                      ws, s);
+    if (e != hipSuccess) return e;
+    e = run_chain(prec, N, 2 * np, p, ws, s);
+    if (e != hipSuccess) return e;
+    const long long nout = 2LL * np * N * N;
+    StageTimer tm(6, s);
+    hipLaunchKernelGGL(k_reduce_sigma, dim3(blocks(nout, 256)), dim3(256), 0, s, N, 2 * np, p.nz,
+                       reinterpret_cast<const cplx*>(at(ws, p.part)), (i64)k0, S_less, S_great, O_less,
+                       O_great);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// U[k] = exp(-i h (T-k) dt), k = 0..T-1: U_1 by scaling and squaring, then the
+// powers U_1^m by doubling (P_{L+i} = P_L P_i), one batched product per level.
+hipError_t propagators(int N, int T, const void* h, double dt, cplx* U, cplx* ex1, cplx* ex2, hipStream_t s) {
+  const i64 nn = (i64)N * N;
+  hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, reinterpret_cast<const cplx*>(h), 0.0, -dt,
+                     U + (T - 1) * nn, ex1, ex2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int L = 1; L < T; L *= 2) {
+    const int cnt = L < T - L ? L : T - L;
+    GemmArgs g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = U + (T - L) * nn; g.sAm = N; g.sAk = 1; g.sAbh = 0;
+    g.B = U + (T - 1) * nn; g.sBk = N; g.sBn = 1; g.sBbh = -nn;
+    g.C = U + (T - L - 1) * nn; g.sCm = N; g.sCn = 1; g.sCbh = -nn;
+    e = zgemm(g, cnt, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* sb2_version(void) { return "sb2 0.1 (gfx950)"; }
+
+int sb2_profile_enable(int on) {
+  g_prof.on = on != 0;
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  return SB2_OK;
+}
+
+int sb2_profile_read(double* ms, int* launches, int nslots) {
+  if (!ms || !launches || nslots < 1) return SB2_EINVAL;
+  for (int i = 0; i < nslots; ++i) { ms[i] = 0.0; launches[i] = 0; }
+  for (const ProfRec& r : g_prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return SB2_EHIP;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return SB2_EHIP;
+    if (r.slot < nslots) { ms[r.slot] += t; launches[r.slot] += 1; }
+  }
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  return SB2_OK;
+}
+
+const char* sb2_status_string(int status) {
+  switch (status) {
+    case SB2_OK: return "ok";
+    case SB2_EINVAL: return "invalid argument (null pointer, non-finite or non-positive dt, or unknown enum)";
+    case SB2_ESHAPE: return "size out of range (N, T or batch count)";
+    case SB2_EWORKSPACE: return "workspace smaller than sb2_workspace_size()";
+    case SB2_EHIP: return "HIP runtime error while enqueueing work";
+    case SB2_EUNSUPPORTED: return "precision not supported by this entry point";
+    default: return "unknown status";
+  }
+}
+
+size_t sb2_workspace_size(int op, int N, int T, int prec) {
+  if (N < 1 || N > SB2_MAX_N || !prec_ok(prec)) return 0;
+  switch (op) {
+    case SB2_OP_SIGMA:
+      if (T < 1) return 0;
+      return chain_plan(N, T, prec, 0).end;
+    case SB2_OP_COLLISION:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return coll_plan(N, T, prec).end;
+    case SB2_OP_RHO_STEP:
+      return rho_plan(N);
+    default:
+      return 0;
+  }
+}
+
+int sb2_sigma(int N, int B, const double* v, const void* Gl, const void* Gg, void* Sl, void* Sg, int prec,
+              void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || B < 1) return SB2_ESHAPE;
+  if (!v || !Gl || !Gg || !Sl || !Sg || !ws || !prec_ok(prec)) return SB2_EINVAL;
+  const ChainPlan p = chain_plan(N, B, prec, 0);
+  if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = sigma_pairs(prec, N, B, v, Gl, Gg, nullptr, nullptr, 1, reinterpret_cast<cplx*>(Sl),
+                             reinterpret_cast<cplx*>(Sg), nullptr, nullptr, p, ws, s);
+  return e == hipSuccess ? SB2_OK : SB2_EHIP;
+}
+
+int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, void* I_out,
+                  void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  const CollPlan c = coll_plan(N, T, prec);
+  if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const i64 nn = (i64)N * N;
+  cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
+  cplx* X = reinterpret_cast<cplx*>(at(ws, c.X));
+  cplx* Y = reinterpret_cast<cplx*>(at(ws, c.Y));
+  cplx* Gl = reinterpret_cast<cplx*>(at(ws, c.Gl));
+  cplx* Gg = reinterpret_cast<cplx*>(at(ws, c.Gg));
+  cplx* Glb = reinterpret_cast<cplx*>(at(ws, c.Glb));
+  cplx* Ggb = reinterpret_cast<cplx*>(at(ws, c.Ggb));
+  cplx* Sl = reinterpret_cast<cplx*>(at(ws, c.Sl));
+  cplx* Sg = reinterpret_cast<cplx*>(at(ws, c.Sg));
+  cplx* terms = reinterpret_cast<cplx*>(at(ws, c.terms));
+
+  GemmArgs g;
+  {
+  StageTimer tm(5, s);
+  if (propagators(N, T, h, dt, U, reinterpret_cast<cplx*>(at(ws, c.ex1)), reinterpret_cast<cplx*>(at(ws, c.ex2)),
+                  s) != hipSuccess)
+    return SB2_EHIP;
+  // X_k = U_k rho_k ; Y_k = rho_k U_k^dag
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = U; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+  g.B = rho_hist; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+  g.C = X; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+  SB2_TRY(zgemm(g, T, s));
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = rho_hist; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+  g.B = U; g.sBk = 1; g.sBn = N; g.sBbh = nn; g.conjB = 1;
+  g.C = Y; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+  SB2_TRY(zgemm(g, T, s));
+  hipLaunchKernelGGL(k_gkba, dim3(blocks((long long)T * nn, 256)), dim3(256), 0, s, N, T, U, X, Y, Gl, Gg, Glb,
+                     Ggb);
+  SB2_TRY(hipGetLastError());
+  }
+
+  cplx* Ol = Sigma_out ? reinterpret_cast<cplx*>(Sigma_out) : nullptr;
+  cplx* Og = Sigma_out ? Ol + (i64)T * nn : nullptr;
+  SB2_TRY(sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s));
+
+  // terms_k = Sigma^>_k G^<(t_k,t) - Sigma^<_k G^>(t_k,t)
+  StageTimer tm(7, s);
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = Sg; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+  g.B = Glb; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+  g.C = terms; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+  SB2_TRY(zgemm(g, T, s));
+  g.A = Sl; g.B = Ggb; g.alpha_re = -1.0; g.beta1 = 1;
+  SB2_TRY(zgemm(g, T, s));
+  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt,
+                     reinterpret_cast<cplx*>(I_out));
+  SB2_TRY(hipGetLastError());
+  return SB2_OK;
+}
+
+int sb2_rho_step(int N, const void* h, const void* rho, const void* I, double dt, void* rho_out, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N) return SB2_ESHAPE;
+  if (!h || !rho || !I || !rho_out || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  if (ws_bytes < rho_plan(N)) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t m = al((size_t)N * N * C128);
+  cplx* U = reinterpret_cast<cplx*>(at(ws, 0));
+  cplx* T1 = reinterpret_cast<cplx*>(at(ws, m));
+  cplx* ex1 = reinterpret_cast<cplx*>(at(ws, 2 * m));
+  cplx* ex2 = reinterpret_cast<cplx*>(at(ws, 3 * m));
+  hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, reinterpret_cast<const cplx*>(h), 0.0, -dt, U,
+                     ex1, ex2);
+  SB2_TRY(hipGetLastError());
+  GemmArgs g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = U; g.sAm = N; g.sAk = 1;
+  g.B = rho; g.sBk = N; g.sBn = 1;
+  g.C = T1; g.sCm = N; g.sCn = 1;
+  SB2_TRY(zgemm(g, 1, s));
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = T1; g.sAm = N; g.sAk = 1;
+  g.B = U; g.sBk = 1; g.sBn = N; g.conjB = 1;
+  g.C = ex1; g.sCm = N; g.sCn = 1;
+  SB2_TRY(zgemm(g, 1, s));
+  hipLaunchKernelGGL(k_rho_finish, dim3(blocks((long long)N * N, 256)), dim3(256), 0, s, N, ex1,
+                     reinterpret_cast<const cplx*>(I), dt, reinterpret_cast<cplx*>(rho_out));
+  SB2_TRY(hipGetLastError());
+  return SB2_OK;
+}
+
+int sb2_collision_backward(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
+                           const void* gI, double* gv, void* gh, void* grho, int prec, void* ws,
+                           size_t ws_bytes, void* stream) {
+  (void)v; (void)h; (void)rho_hist; (void)gI; (void)gv; (void)gh; (void)grho; (void)ws; (void)ws_bytes;
+  (void)stream; (void)dt;
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (prec != SB2_FP64) return SB2_EUNSUPPORTED;
+  return SB2_EUNSUPPORTED;
+}
+
+size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec) {
+  if (nsys < 1 || !sys || !prec_ok(prec)) return 0;
+  size_t tot = 0;
+  for (int b = 0; b < nsys; ++b) {
+    const size_t w = sb2_workspace_size(SB2_OP_COLLISION, sys[b].N, sys[b].T, prec);
+    if (w == 0) return 0;
+    tot += w;
+  }
+  return tot;
+}
+
+int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (nsys < 1 || !sys || !ws || !prec_ok(prec)) return SB2_EINVAL;
+  for (int b = 0; b < nsys; ++b) {
+    const sb2_system& q = sys[b];
+    if (q.N < 1 || q.N > SB2_MAX_N || q.T < 1 || q.T > SB2_MAX_T) return SB2_ESHAPE;
+    if (!q.v || !q.h || !q.rho_hist || !q.I_out || !finite_pos(q.dt)) return SB2_EINVAL;
+  }
+  if (ws_bytes < sb2_batched_workspace_size(nsys, sys, prec)) return SB2_EWORKSPACE;
+  size_t off = 0;
+  for (int b = 0; b < nsys; ++b) {
+    const sb2_system& q = sys[b];
+    const size_t w = sb2_workspace_size(SB2_OP_COLLISION, q.N, q.T, prec);
+    const int st = sb2_collision(q.N, q.T, q.v, q.h, q.rho_hist, q.dt, q.I_out, nullptr, prec,
+                                 at(ws, off), w, stream);
+    if (st != SB2_OK) return st;
+    off += w;
+  }
+  return SB2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: float64 path to 1e-11 relative (max-abs error over max-abs value);
+float32 and split-float16 paths to 2e-6 on the self-energies and the collision
+integral at these sizes (the full-size precision figure is measured by the
+benchmark and by test_gpu_fullsize).  Sizes span several 16-wide MFMA tiles
+and ragged tails (N = 1, 2, 5, 17, 33, 37, T up to 41).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sb2_oracle as o
+from paper_1905_01180_amd import inputs as gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = {"fp64": 1e-11, "fp32": 2e-6, "fp16x3": 2e-6}
+
+
+def rel(a, b):
+    a = a.detach().cpu().numpy() if hasattr(a, "detach") else a
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def lib():
+    from paper_1905_01180_amd import _lib
+    return _lib
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_collision_c0_golden(prec):
+    z = np.load(os.path.join(GOLDEN, "oracle_c0.npz"))
+    s = gen.make_config(0)
+    say("case: C0 N=10 T=20", prec)
+    i_ns, sig = lib().sb2_collision(dev(s.v), dev(s.h), dev(s.rho_hist), s.dt, prec, return_sigma=True)
+    torch.cuda.synchronize()
+    assert rel(i_ns, z["i_ns"]) < TOL[prec]
+    sig = sig.cpu().numpy()
+    for idx, k in enumerate(z["sigma_ks"]):
+        assert rel(sig[0, k], z["sigma_less"][idx]) < TOL[prec]
+        assert rel(sig[1, k], z["sigma_great"][idx]) < TOL[prec]
+
+
+@pytest.mark.parametrize("n,b", [(1, 1), (2, 3), (5, 2), (17, 3), (33, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_sigma_random_pairs(n, b, prec):
+    g = np.random.default_rng(1000 + n)
+    v = gen.interaction_generic(n, g)
+    gl = g.standard_normal((b, n, n)) + 1j * g.standard_normal((b, n, n))
+    gg = g.standard_normal((b, n, n)) + 1j * g.standard_normal((b, n, n))
+    say("case: sigma N=%d B=%d" % (n, b), prec)
+    sl, sg = lib().sb2_sigma(dev(v), dev(gl), dev(gg), prec)
+    torch.cuda.synchronize()
+    sl, sg = sl.cpu().numpy(), sg.cpu().numpy()
+    for k in range(b):
+        want_l = o.sigma(v, gl[k], -gg[k].conj().T)
+        want_g = o.sigma(v, gg[k], -gl[k].conj().T)
+        assert rel(sl[k], want_l) < TOL[prec], (k, rel(sl[k], want_l))
+        assert rel(sg[k], want_g) < TOL[prec], (k, rel(sg[k], want_g))
+
+
+@pytest.mark.parametrize("n,t", [(2, 3), (17, 9), (20, 41), (37, 6)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_collision_against_oracle(n, t, prec):
+    s = gen.make_system(n, t, config_id=200, system_id=n)
+    want, ref_sig = o.collision(s.v, s.h, s.rho_hist, s.dt, return_sigma=True)
+    say("case: collision N=%d T=%d" % (n, t), prec)
+    got, sig = lib().sb2_collision(dev(s.v), dev(s.h), dev(s.rho_hist), s.dt, prec, return_sigma=True)
+    torch.cuda.synchronize()
+    assert rel(got, want) < TOL[prec], rel(got, want)
+    sig = sig.cpu().numpy()
+    for k in (0, t // 2, t - 1):
+        assert rel(sig[0, k], ref_sig[k][0]) < TOL[prec]
+        assert rel(sig[1, k], ref_sig[k][1]) < TOL[prec]
+
+
+def test_zero_interaction_gives_exact_zero():
+    s = gen.make_system(9, 5, config_id=201)
+    say("case: v=0 N=9 T=5")
+    for prec in ("fp64", "fp32", "fp16x3"):
+        got = lib().sb2_collision(dev(np.zeros_like(s.v)), dev(s.h), dev(s.rho_hist), s.dt, prec)
+        torch.cuda.synchronize()
+        assert float(got.abs().max()) == 0.0
+
+
+def test_conservation_on_gpu():
+    # tr(I + I^dag) = 0 for v with the {jilk, klij} symmetries (holds per past time)
+    s = gen.make_system(24, 30, config_id=202)
+    say("case: conservation N=24 T=30")
+    for prec in ("fp64", "fp32", "fp16x3"):
+        got = lib().sb2_collision(dev(s.v), dev(s.h), dev(s.rho_hist), s.dt, prec).cpu().numpy()
+        tr = np.trace(got + got.conj().T)
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        assert abs(tr) < tol * np.abs(got).sum(), (prec, tr)
+
+
+def test_rho_step_against_oracle():
+    s = gen.make_system(13, 7, config_id=203)
+    i_ns = o.collision(s.v, s.h, s.rho_hist, s.dt)
+    rho = s.rho_hist[-1]
+    say("case: rho step N=13")
+    got = lib().sb2_rho_step(dev(s.h), dev(rho), dev(i_ns), s.dt)
+    torch.cuda.synchronize()
+    want = o.rho_step(s.h, rho, i_ns, s.dt)
+    assert rel(got, want) < 1e-12
+    # a propagator with many squarings (large ||h dt||)
+    h_big = 40.0 * s.h
+    got = lib().sb2_rho_step(dev(h_big), dev(rho), dev(i_ns), s.dt)
+    assert rel(got, o.rho_step(h_big, rho, i_ns, s.dt)) < 1e-11
+
+
+def test_determinism():
+    s = gen.make_system(21, 12, config_id=204)
+    say("case: determinism N=21 T=12")
+    for prec in ("fp64", "fp32", "fp16x3"):
+        a = lib().sb2_collision(dev(s.v), dev(s.h), dev(s.rho_hist), s.dt, prec)
+        b = lib().sb2_collision(dev(s.v), dev(s.h), dev(s.rho_hist), s.dt, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), prec
