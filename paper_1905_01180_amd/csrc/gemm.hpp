@@ -57,11 +57,21 @@ struct GemmArgs {
 };
 
 // ---------------------------------------------------------------------------
-// MFMA wrappers (16x16 output fragment; lane l holds rows 4(l/16)+i, col l%16)
+// MFMA wrappers.  Inputs (16x16xK): lane l supplies A[l%16][k] and B[k][l%16]
+// for k = l/16 (K = 4) or k = 8(l/16)..8(l/16)+7 (K = 32).  Output fragment:
+// lane l holds column l%16 and, in accumulator slot q, row
+//   f32 / f16 instructions:  4 (l/16) + q
+//   f64 instruction:         (l/16) + 4 q
+// (checked with a lane-layout probe on gfx950).
 // ---------------------------------------------------------------------------
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = dx4; };
 template <> struct Acc<float> { using type = fx4; };
+
+// row of accumulator slot q held by lane group kq = l/16
+template <typename T> __device__ __forceinline__ int frag_row(int kq, int q);
+template <> __device__ __forceinline__ int frag_row<double>(int kq, int q) { return kq + 4 * q; }
+template <> __device__ __forceinline__ int frag_row<float>(int kq, int q) { return 4 * kq + q; }
 
 __device__ __forceinline__ dx4 mma(double a, double b, dx4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -335,7 +345,7 @@ k_gemm(const GemmArgs g) {
     for (int j = 0; j < FN; ++j) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = wrow0 + i * 16 + 4 * kq + q;
+        const int m = wrow0 + i * 16 + frag_row<T>(kq, q);
         const int n = wcol0 + j * 16 + lr;
         if (m < g.M && n < g.N) {
           double re, im;
@@ -504,7 +514,7 @@ k_gemm_h16(const GemmArgs g) {
     for (int j = 0; j < FN; ++j) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = wrow0 + i * 16 + 4 * kq + q;
+        const int m = wrow0 + i * 16 + frag_row<float>(kq, q);
         const int n = wcol0 + j * 16 + lr;
         if (m < g.M && n < g.N) {
           double re, im;
