@@ -185,13 +185,15 @@ __global__ void k_gkba(int N, int T, const cplx* __restrict__ U, const cplx* __r
 // Per-chunk operand packing.  Slice b = 2 (k - k0) + sigma holds
 //   sigma = 0:  G = G^<(t,t_k), Gbar = G^>(t_k,t)   (-> Sigma^<)
 //   sigma = 1:  G = G^>(t,t_k), Gbar = G^<(t_k,t)   (-> Sigma^>)
-// cast to the bulk precision T.  When gbar_from_g is set, Gbar is formed as
-// -G'^dag from the opposite-kind function (Gl, Gg are then per-pair inputs).
+// cast to the bulk type T; G is stored as G[b][n][m], Gbar transposed as
+// GbT[b][r][s] = Gbar_sr (both K-contiguous for the contraction kernels).
+// When gbar_from_g is set, Gbar is formed as -G'^dag from the opposite-kind
+// input (per-pair inputs of the self-energy entry point).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cplx* __restrict__ Gg,
                        const cplx* __restrict__ Glb, const cplx* __restrict__ Ggb, int gbar_from_g,
-                       T* __restrict__ Gs, T* __restrict__ Gbs, unsigned* gmax, unsigned* gbmax) {
+                       T* __restrict__ Gs, T* __restrict__ GbT, unsigned* gmax, unsigned* gbmax) {
   const i64 nn = (i64)N * N;
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   float mg = 0.f, mb = 0.f;
@@ -201,19 +203,20 @@ __global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cpl
     const int i = r / N, j = r - (r / N) * N;
     const i64 kp = b >> 1;
     const int sig = (int)(b & 1);
-    const cplx g = sig == 0 ? Gl[kp * nn + r] : Gg[kp * nn + r];
+    const cplx gv = sig == 0 ? Gl[kp * nn + r] : Gg[kp * nn + r];
+    // Gbar element (j, i) goes to GbT[b][i][j]
     cplx gb;
     if (gbar_from_g) {
-      const cplx o = sig == 0 ? Gg[kp * nn + (i64)j * N + i] : Gl[kp * nn + (i64)j * N + i];
-      gb = mk(-o[0], o[1]);                     // -conj(o_ji)
+      const cplx o = sig == 0 ? Gg[kp * nn + r] : Gl[kp * nn + r];   // Gbar_ji = -conj(o_ij)
+      gb = mk(-o[0], o[1]);
     } else {
-      gb = sig == 0 ? Ggb[kp * nn + r] : Glb[kp * nn + r];
+      gb = sig == 0 ? Ggb[kp * nn + (i64)j * N + i] : Glb[kp * nn + (i64)j * N + i];
     }
-    Gs[2 * e] = (T)g[0];
-    Gs[2 * e + 1] = (T)g[1];
-    Gbs[2 * e] = (T)gb[0];
-    Gbs[2 * e + 1] = (T)gb[1];
-    mg = fmaxf(fabsf((float)g[0]), fabsf((float)g[1]));
+    Gs[2 * e] = (T)gv[0];
+    Gs[2 * e + 1] = (T)gv[1];
+    GbT[2 * e] = (T)gb[0];
+    GbT[2 * e + 1] = (T)gb[1];
+    mg = fmaxf(fabsf((float)gv[0]), fabsf((float)gv[1]));
     mb = fmaxf(fabsf((float)gb[0]), fabsf((float)gb[1]));
   }
   if (gmax) {
@@ -224,60 +227,106 @@ __global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cpl
 }
 
 // ---------------------------------------------------------------------------
-// Interaction layouts for the contraction chain (one workgroup per N x N
-// block, transposed through LDS):
-//   W[m][q][j][s]  = 2 v_mqsj - v_qmsj     (right-hand vertex, exchange folded in)
-//   Vp[i][n][p][r] = v_irpn                (left-hand vertex, contraction index (n,p,r))
+// Interaction layouts for the contraction chain:
+//   W_T[x][m], x = (j N + s) N + q:  w_mqsj = 2 v_mqsj - v_qmsj   (row pitch KpW)
+//   V'[i][k],  k = (n N + p) N + r:  v_irpn                        (row pitch KpV)
+// Stored in the bulk type, or (split float16) as hi / lo planes of
+// x 2^e with 2^e from the recorded max (two passes: k_max_vw, then the writers).
 // ---------------------------------------------------------------------------
-// 32 x 32 LDS-tiled transpose of one N x N block: out[c][r] = f(in[r][c]).
-template <typename T>
-__device__ __forceinline__ float transpose_block(int N, const double* __restrict__ a, i64 sar,
-                                                 const double* __restrict__ b, i64 sbr, double cb,
-                                                 T* __restrict__ out, i64 sor) {
-  __shared__ T tile[32][33];
-  float mx = 0.f;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 256 threads: 32 x 8
-  for (int r0 = 0; r0 < N; r0 += 32)
-    for (int c0 = 0; c0 < N; c0 += 32) {
-      __syncthreads();
-      for (int yy = ty; yy < 32; yy += 8) {
-        const int r = r0 + yy, c = c0 + tx;
-        if (r < N && c < N) {
-          double x = a[r * sar + c];
-          if (b) x = 2.0 * x - cb * b[r * sbr + c];
-          tile[yy][tx] = (T)x;
-          mx = fmaxf(mx, fabsf((float)x));
-        }
-      }
-      __syncthreads();
-      for (int yy = ty; yy < 32; yy += 8) {
-        const int c = c0 + yy, r = r0 + tx;
-        if (r < N && c < N) out[c * sor + r] = tile[tx][yy];
-      }
-    }
-  return mx;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_prep_w(int N, const double* __restrict__ v, T* __restrict__ W,
-                                                unsigned* wmax) {
+__global__ void __launch_bounds__(256) k_max_vw(int N, const double* __restrict__ v, unsigned* vmax,
+                                                 unsigned* wmax) {
   const int m = blockIdx.x / N, q = blockIdx.x % N;
   const i64 nn = (i64)N * N;
-  // rows s, cols j of v[m][q][s][j] and v[q][m][s][j]; out rows j, cols s of W[m][q][j][s]
-  const float mx = transpose_block<T>(N, v + ((i64)m * N + q) * nn, N, v + ((i64)q * N + m) * nn, N, 1.0,
-                                      W + ((i64)m * N + q) * nn, N);
-  if (wmax) block_atomic_max(mx, wmax);
+  const double* a = v + ((i64)m * N + q) * nn;
+  const double* b = v + ((i64)q * N + m) * nn;
+  float mv = 0.f, mw = 0.f;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    mv = fmaxf(mv, fabsf((float)a[e]));
+    mw = fmaxf(mw, fabsf((float)(2.0 * a[e] - b[e])));
+  }
+  block_atomic_max(mv, vmax);
+  __syncthreads();
+  block_atomic_max(mw, wmax);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_prep_vp(int N, const double* __restrict__ v, T* __restrict__ Vp,
-                                                 unsigned* vmax) {
+__device__ __forceinline__ void put_val(T* base, i64 plane, i64 idx, double x, float sc) {
+  base[idx] = (T)x;
+}
+template <>
+__device__ __forceinline__ void put_val<_Float16>(_Float16* base, i64 plane, i64 idx, double x, float sc) {
+  const float y = (float)x * sc;
+  const _Float16 hi = (_Float16)y;
+  base[idx] = hi;
+  base[plane + idx] = (_Float16)(y - (float)hi);
+}
+
+// one workgroup per (s, j-block of 16, m-block of 8); LDS tile [q][j][m]
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* __restrict__ v, T* __restrict__ W,
+                                                  i64 plane, const unsigned* wmax) {
+  __shared__ float tile[128][16][9];
+  const int nj = (N + 15) / 16, nm = (N + 7) / 8;
+  const int s = blockIdx.x / (nj * nm);
+  const int rem = blockIdx.x - s * nj * nm;
+  const int j0 = (rem / nm) * 16, m0 = (rem % nm) * 8;
+  const i64 nn = (i64)N * N;
+  const float sc = split_scale(wmax);
+  // read: for (mm, q): 16 consecutive j of v[m][q][s][j] and v[q][m][s][j]
+  for (int L = threadIdx.x; L < 8 * N * 16; L += blockDim.x) {
+    const int jj = L & 15, mq = L >> 4;
+    const int mm = mq / N, q = mq - (mq / N) * N;
+    const int m = m0 + mm, j = j0 + jj;
+    float w = 0.f;
+    if (m < N && j < N) {
+      const double a = v[((i64)m * N + q) * nn + (i64)s * N + j];
+      const double b = v[((i64)q * N + m) * nn + (i64)s * N + j];
+      w = (float)(2.0 * a - b);
+      if constexpr (sizeof(T) == 8) w = 0.f;    // float64 path re-reads below in full precision
+    }
+    tile[q][jj][mm] = w;
+  }
+  __syncthreads();
+  // write rows x = (j, s, q), elements m0..m0+7
+  for (int L = threadIdx.x; L < 16 * N * 8; L += blockDim.x) {
+    const int mm = L & 7, jq = L >> 3;
+    const int jj = jq / N, q = jq - (jq / N) * N;
+    const int m = m0 + mm, j = j0 + jj;
+    if (m < N && j < N) {
+      const i64 x = ((i64)j * N + s) * N + q;
+      double val;
+      if constexpr (sizeof(T) == 8) {
+        val = 2.0 * v[((i64)m * N + q) * nn + (i64)s * N + j] - v[((i64)q * N + m) * nn + (i64)s * N + j];
+      } else {
+        val = tile[q][jj][mm];
+      }
+      put_val<T>(W, plane, x * KpW + m, val, sc);
+    }
+  }
+}
+
+// one workgroup per (i, p): 32 x 32 LDS transposes of the (r, n) block
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep_vpt(int N, i64 KpV, const double* __restrict__ v, T* __restrict__ Vp,
+                                                   i64 plane, const unsigned* vmax) {
+  __shared__ double tile[32][33];
   const int i = blockIdx.x / N, p = blockIdx.x % N;
   const i64 nn = (i64)N * N;
-  // rows r (stride N^2), cols n of v[i][r][p][n]; out rows n (stride N^2), cols r of Vp[i][n][p][r]
-  const float mx = transpose_block<T>(N, v + (i64)i * N * nn + (i64)p * N, nn, nullptr, 0, 0.0,
-                                      Vp + (i64)i * N * nn + (i64)p * N, nn);
-  if (vmax) block_atomic_max(mx, vmax);
+  const float sc = split_scale(vmax);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r0 = 0; r0 < N; r0 += 32)
+    for (int n0 = 0; n0 < N; n0 += 32) {
+      __syncthreads();
+      for (int yy = ty; yy < 32; yy += 8) {
+        const int r = r0 + yy, n = n0 + tx;
+        tile[yy][tx] = (r < N && n < N) ? v[(((i64)i * N + r) * N + p) * N + n] : 0.0;
+      }
+      __syncthreads();
+      for (int yy = ty; yy < 32; yy += 8) {
+        const int n = n0 + yy, r = r0 + tx;
+        if (r < N && n < N) put_val<T>(Vp, plane, (i64)i * KpV + ((i64)n * N + p) * N + r, tile[tx][yy], sc);
+      }
+    }
 }
 
 // ---------------------------------------------------------------------------

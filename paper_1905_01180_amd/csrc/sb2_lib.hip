@@ -3,15 +3,16 @@
 // Contraction chain (Eq. 13 regrouped; Eq. 19 / Fig. 2 give the paper's own
 // path, this is another valid one).  With w_mqsj = 2 v_mqsj - v_qmsj,
 //   Sigma_ij = sum v_irpn w_mqsj G_nm G_pq Gbar_sr
-// is evaluated per slice (pair of times, kind <>) as four GEMMs whose big
-// operand is always contiguous:
-//   R1  A[n][q][j][s] = sum_m G_nm W[m][q][j][s]            (slices stacked: M = 2S N)
-//   R2  B[n][p][j][s] = sum_q G_pq A[n][q][j][s]            (batched over (slice, n))
-//   R3  C[j][n][p][r] = sum_s B[n][p][j][s] Gbar_sr         (batched over slices)
+// is evaluated per slice (pair of times, kind <>) as four contractions in which
+// both operands are contiguous along the summed index:
+//   R1  A[n][j][s][q] = sum_m G_nm  W_T[j][s][q][m]              (slices stacked: rows 2S N)
+//   R2  B[n][p][j][s] = sum_q G_pq  A[n][j][s][q]                (batched over (slice, n))
+//   R3  C[j][n][p][r] = sum_s B[n][p][j][s] GbT[r][s]            (batched over slices)
 //   R4  Sigma_ij      = sum_{(n,p,r)} Vp[i][n][p][r] C[j][n][p][r]   (split-K, float64 partials)
-// with the interaction laid out once per call as W[m][q][j][s] = w_mqsj and
-// Vp[i][n][p][r] = v_irpn.  R1 and R4 share W / Vp across all slices of a chunk
-// of past times; the intermediates A/C and B each take 2S N^4 complex entries.
+// with the interaction laid out once per call as W_T[j][s][q][m] = w_mqsj and
+// Vp[i][n][p][r] = v_irpn, and GbT[r][s] = Gbar_sr.  R1 and R4 share W_T / Vp
+// across all slices of a chunk of past times; the intermediates A/C and B each
+// take 2S N^4 complex entries.  Each stage is one k_stream launch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,6 +21,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "stream_gemm.hpp"
 #include "sb2.h"
 
 using namespace sb2;
@@ -82,13 +84,17 @@ hipError_t zgemm(GemmArgs g, int nbatch, hipStream_t s) {
 // ---------------------------------------------------------------------------
 struct ChainPlan {
   int N = 0, S = 0, nz = 1, kchunk = 1;
+  i64 KpW = 0, KpV = 0;                 // row pitches of W_T and Vp
   size_t w = 0, vp = 0, gs = 0, gbs = 0, x1 = 0, x2 = 0, part = 0, scal = 0, end = 0;
 };
+
+inline int slab_depth(int prec) { return prec == SB2_SPLIT_FP16 ? 128 : prec == SB2_FP32 ? 64 : 32; }
+inline size_t inter_bytes(int prec) { return prec == SB2_SPLIT_FP16 ? 4 : bulk_bytes(prec); }  // W_T / Vp per element
 
 // R4 split-K: enough workgroups to fill the chip, chunk a multiple of the slab depth.
 void r4_split(int N, int ns, int prec, int& nz, int& kchunk) {
   const long long K = (long long)N * N * N;
-  const int bk = prec == SB2_SPLIT_FP16 ? 32 : 16;
+  const int bk = slab_depth(prec);
   const long long coltiles = ((long long)ns * N + 63) / 64;
   const long long rowtiles = (N + 111) / 112;
   long long want = (2048 + coltiles * rowtiles - 1) / (coltiles * rowtiles);
@@ -105,20 +111,23 @@ void r4_split(int N, int ns, int prec, int& nz, int& kchunk) {
 ChainPlan chain_plan(int N, int pairs, int prec, size_t base) {
   ChainPlan p;
   p.N = N;
-  const size_t n4 = (size_t)N * N * N * N, n2 = (size_t)N * N;
+  const size_t n4 = (size_t)N * N * N * N, n3 = (size_t)N * N * N, n2 = (size_t)N * N;
   const size_t bb = bulk_bytes(prec);
   const size_t per_pair = 2 * 2 * n4 * 2 * bb;      // two buffers x two slices x N^4 complex
   size_t S = INTERMEDIATE_BUDGET / per_pair;
   if (S < 1) S = 1;
   if (S > (size_t)pairs) S = pairs;
-  const size_t smax = 65535 / (2 * (size_t)N);       // R2 batch = 2 S N launches in grid.y
+  const size_t smax = 65535 / (2 * (size_t)N);       // R2 batch = 2 S N workgroup rows in grid.y
   if (S > smax) S = smax;
   p.S = (int)S;
+  p.KpW = (N + 7) / 8 * 8;
+  p.KpV = ((i64)n3 + 7) / 8 * 8;
   r4_split(N, 2 * p.S, prec, p.nz, p.kchunk);
+  const size_t ib = inter_bytes(prec);
   size_t o = base;
   p.scal = o; o += al(S_NWORDS * 4);
-  p.w = o; o += al(n4 * bb);
-  p.vp = o; o += al(n4 * bb);
+  p.w = o; o += al(n3 * (size_t)p.KpW * ib);
+  p.vp = o; o += al((size_t)N * (size_t)p.KpV * ib);
   p.gs = o; o += al(2 * S * n2 * 2 * bb);
   p.gbs = o; o += al(2 * S * n2 * 2 * bb);
   p.x1 = o; o += al(2 * S * n4 * 2 * bb);
@@ -217,18 +226,49 @@ hipError_t prep_interaction(int N, const double* v, const ChainPlan& p, void* ws
   unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scal, (int)S_NWORDS, 0u);
   const bool h = prec == SB2_SPLIT_FP16;
-  hipLaunchKernelGGL(k_prep_w<T>, dim3(N * N), dim3(256), 0, s, N, v, reinterpret_cast<T*>(at(ws, p.w)),
-                     h ? scal + S_WMAX : nullptr);
-  hipLaunchKernelGGL(k_prep_vp<T>, dim3(N * N), dim3(256), 0, s, N, v, reinterpret_cast<T*>(at(ws, p.vp)),
-                     h ? scal + S_VMAX : nullptr);
+  if (h) hipLaunchKernelGGL(k_max_vw, dim3(N * N), dim3(256), 0, s, N, v, scal + S_VMAX, scal + S_WMAX);
+  const int nj = (N + 15) / 16, nm = (N + 7) / 8;
+  const i64 planeW = (i64)N * N * N * p.KpW, planeV = (i64)N * p.KpV;
+  hipLaunchKernelGGL(k_prep_wt<T>, dim3(N * nj * nm), dim3(256), 0, s, N, (int)p.KpW, v,
+                     reinterpret_cast<T*>(at(ws, p.w)), planeW, h ? scal + S_WMAX : nullptr);
+  hipLaunchKernelGGL(k_prep_vpt<T>, dim3(N * N), dim3(256), 0, s, N, p.KpV, v, reinterpret_cast<T*>(at(ws, p.vp)),
+                     planeV, h ? scal + S_VMAX : nullptr);
   return hipGetLastError();
+}
+
+constexpr int PERSIST_TARGET = 768;   // workgroups per launch when shared tiles stay resident
+
+template <int PK, bool SA, bool SC, bool XC, int FS, int FX, int NW, int KS, bool ACC64, typename OutT>
+hipError_t launch_s(StreamArgs g, int nbatch, hipStream_t st) {
+  constexpr int SR = 16 * FS, XT = 16 * FX * NW;
+  if (g.kchunk <= 0) g.kchunk = g.K > 0 ? g.K : 1;
+  const int slim = SA ? g.M : g.N, xlim = SA ? g.N : g.M;
+  const int tiles_s = (slim + SR - 1) / SR, tiles_x = (xlim + XT - 1) / XT;
+  g.tiles_m = tiles_s;
+  int npersist = tiles_x;
+  if (g.kchunk <= KS) {
+    const long long want = (PERSIST_TARGET + (long long)tiles_s * nbatch - 1) / ((long long)tiles_s * nbatch);
+    npersist = (int)(want < 1 ? 1 : (want > tiles_x ? tiles_x : want));
+  }
+  const int nz = g.K > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
+  dim3 grid(tiles_s * npersist, nbatch, nz);
+  hipLaunchKernelGGL((k_stream<PK, SA, SC, XC, FS, FX, NW, KS, ACC64, OutT>), grid, dim3(64 * NW), 0, st, g);
+  return hipGetLastError();
+}
+
+StreamArgs sdef() {
+  StreamArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nbl = 1;
+  g.kpromote = 4;
+  return g;
 }
 
 hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipStream_t st) {
   const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
   unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
   const void* Gs = at(ws, p.gs);
-  const void* Gbs = at(ws, p.gbs);
+  const void* GbT = at(ws, p.gbs);
   const void* W = at(ws, p.w);
   const void* Vp = at(ws, p.vp);
   void* X1 = at(ws, p.x1);
@@ -237,63 +277,63 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   const bool h16 = prec == SB2_SPLIT_FP16;
   hipError_t e;
 
-  // R1: A[(b,n)][(q,j,s)] = sum_m G[(b,n)][m] W[m][(q,j,s)]
-  GemmArgs g = gdef();
+  // R1: A[(b,n)][x] = sum_m G[(b,n)][m] W_T[x][m], x = (j,s,q)
+  StreamArgs g = sdef();
   g.M = ns * N; g.N = (int)n3; g.K = N;
-  g.A = Gs; g.sAm = N; g.sAk = 1;
-  g.B = W; g.sBk = n3; g.sBn = 1;
+  g.S = Gs; g.sSs = N;
+  g.X = W; g.sXx = p.KpW; g.sXplane = n3 * p.KpW;
   g.C = X1; g.sCm = n3; g.sCn = 1;
-  if (h16) { g.amax = scal + S_GMAX; g.bmax = scal + S_WMAX; g.cmax = scal + S_AMAX; }
+  if (h16) { g.smax = scal + S_GMAX; g.xmax = scal + S_WMAX; g.cmax = scal + S_AMAX; }
   {
     StageTimer tm(0, st);
-    if (prec == SB2_FP64) e = launch_f<double, double, 2, 2, 2, 2, true, false, false>(g, 1, st);
-    else if (prec == SB2_FP32) e = launch_f<float, float, 2, 2, 4, 4, true, false, false>(g, 1, st);
-    else e = launch_h<float, 2, 2, 4, 4, true, false, false>(g, 1, st);
+    if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, false, 4, 2, 4, 112, false, double>(g, 1, st);
+    else if (prec == SB2_FP32) e = launch_s<PK_F32, true, true, false, 8, 2, 4, 112, false, float>(g, 1, st);
+    else e = launch_s<PK_H16, true, true, false, 8, 2, 4, 128, false, float>(g, 1, st);
   }
   if (e != hipSuccess) return e;
 
-  // R2: B[b][n][p][(j,s)] = sum_q G_b[p][q] A[b][n][q][(j,s)], batch (b, n)
-  g = gdef();
+  // R2: B[b][n][p][x] = sum_q G_b[p][q] A[b][n][x][q], x = (j,s); batch (b, n)
+  g = sdef();
   g.M = N; g.N = (int)n2; g.K = N; g.nbl = N;
-  g.A = Gs; g.sAm = N; g.sAk = 1; g.sAbh = n2; g.sAbl = 0;
-  g.B = X1; g.sBk = n2; g.sBn = 1; g.sBbh = n4; g.sBbl = n3;
+  g.S = Gs; g.sSs = N; g.sSbh = n2; g.sSbl = 0;
+  g.X = X1; g.sXx = N; g.sXbh = n4; g.sXbl = n3;
   g.C = X2; g.sCm = n2; g.sCn = 1; g.sCbh = n4; g.sCbl = n3;
-  if (h16) { g.amax = scal + S_GMAX; g.bmax = scal + S_AMAX; g.cmax = scal + S_BMAX; }
+  if (h16) { g.smax = scal + S_GMAX; g.xmax = scal + S_AMAX; g.cmax = scal + S_BMAX; }
   {
     StageTimer tm(1, st);
-    if (prec == SB2_FP64) e = launch_f<double, double, 1, 4, 7, 1, true, true, false>(g, ns * N, st);
-    else if (prec == SB2_FP32) e = launch_f<float, float, 1, 4, 7, 1, true, true, false>(g, ns * N, st);
-    else e = launch_h<float, 1, 4, 7, 1, true, true, false>(g, ns * N, st);
+    if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, true, 7, 1, 4, 64, false, double>(g, ns * N, st);
+    else if (prec == SB2_FP32) e = launch_s<PK_F32, true, true, true, 7, 2, 4, 112, false, float>(g, ns * N, st);
+    else e = launch_s<PK_H16, true, true, true, 7, 2, 4, 128, false, float>(g, ns * N, st);
   }
   if (e != hipSuccess) return e;
 
-  // R3: C[b][j][n][p][r] = sum_s B[b][(n,p,j)][s] Gbar_b[s][r], batch b
-  g = gdef();
+  // R3: C[b][j][n][p][r] = sum_s B[b][(n,p,j)][s] GbT[b][r][s]; streamed rows (n,p,j)
+  g = sdef();
   g.M = (int)n3; g.N = N; g.K = N;
-  g.A = X2; g.sAm = N; g.sAk = 1; g.sAbh = n4;
-  g.B = Gbs; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+  g.X = X2; g.sXx = N; g.sXbh = n4;
+  g.S = GbT; g.sSs = N; g.sSbh = n2;
   g.C = X1; g.Mlo = N; g.sCmh = N; g.sCm = n3; g.sCn = 1; g.sCbh = n4;
-  if (h16) { g.amax = scal + S_BMAX; g.bmax = scal + S_GBMAX; g.cmax = scal + S_CMAX; }
+  if (h16) { g.xmax = scal + S_BMAX; g.smax = scal + S_GBMAX; g.cmax = scal + S_CMAX; }
   {
     StageTimer tm(2, st);
-    if (prec == SB2_FP64) e = launch_f<double, double, 4, 1, 1, 7, true, true, false>(g, ns, st);
-    else if (prec == SB2_FP32) e = launch_f<float, float, 4, 1, 1, 7, true, true, false>(g, ns, st);
-    else e = launch_h<float, 4, 1, 1, 7, true, true, false>(g, ns, st);
+    if (prec == SB2_FP64) e = launch_s<PK_F64, false, true, true, 7, 1, 4, 64, false, double>(g, ns, st);
+    else if (prec == SB2_FP32) e = launch_s<PK_F32, false, true, true, 7, 2, 4, 112, false, float>(g, ns, st);
+    else e = launch_s<PK_H16, false, true, true, 7, 2, 4, 128, false, float>(g, ns, st);
   }
   if (e != hipSuccess) return e;
 
-  // R4: part[z][i][c] = sum_{k in chunk z} Vp[i][k] C[c][k], c = b N + j, k = (n,p,r)
-  g = gdef();
+  // R4: part[z][i][x] = sum_{k in chunk z} Vp[i][k] C[x][k], x = b N + j, k = (n,p,r)
+  g = sdef();
   g.M = N; g.N = ns * N; g.K = (int)n3; g.kchunk = p.kchunk;
-  g.A = Vp; g.sAm = n3; g.sAk = 1;
-  g.B = X1; g.sBk = 1; g.sBn = n3;
+  g.S = Vp; g.sSs = p.KpV; g.sSplane = (i64)N * p.KpV;
+  g.X = X1; g.sXx = n3;
   g.C = part; g.sCm = (i64)ns * N; g.sCn = 1; g.sCz = (i64)N * ns * N;
-  if (h16) { g.amax = scal + S_VMAX; g.bmax = scal + S_CMAX; g.kpromote = 2; }
+  if (h16) { g.smax = scal + S_VMAX; g.xmax = scal + S_CMAX; g.kpromote = 2; }
   {
     StageTimer tm(3, st);
-    if (prec == SB2_FP64) e = launch_f<double, double, 1, 4, 7, 1, false, true, false>(g, 1, st);
-    else if (prec == SB2_FP32) e = launch_f<float, double, 1, 4, 7, 1, false, true, true>(g, 1, st);
-    else e = launch_h<double, 1, 4, 7, 1, false, true, true>(g, 1, st);
+    if (prec == SB2_FP64) e = launch_s<PK_F64, true, false, true, 7, 1, 4, 32, false, double>(g, 1, st);
+    else if (prec == SB2_FP32) e = launch_s<PK_F32, true, false, true, 7, 1, 4, 64, true, double>(g, 1, st);
+    else e = launch_s<PK_H16, true, false, true, 7, 1, 4, 128, true, double>(g, 1, st);
   }
   return e;
 }
@@ -320,7 +360,8 @@ hipError_t pack(int N, int npairs, const void* Gl, const void* Gg, const void* G
 hipError_t prep_dispatch(int prec, int N, const double* v, const ChainPlan& p, void* ws, hipStream_t s) {
   StageTimer tm(4, s);
   if (prec == SB2_FP64) return prep_interaction<double>(N, v, p, ws, prec, s);
-  return prep_interaction<float>(N, v, p, ws, prec, s);
+  if (prec == SB2_FP32) return prep_interaction<float>(N, v, p, ws, prec, s);
+  return prep_interaction<_Float16>(N, v, p, ws, prec, s);
 }
 
 hipError_t pack_dispatch(int prec, int N, int np, const void* Gl, const void* Gg, const void* Glb,
