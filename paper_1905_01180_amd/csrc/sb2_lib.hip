@@ -256,6 +256,19 @@ hipError_t launch_s(StreamArgs g, int nbatch, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int PK, bool SA, bool SC, bool XC, int FS, int NW, int KS, typename OutT>
+hipError_t launch_s1(StreamArgs g, int nbatch, hipStream_t st) {
+  constexpr int SR = 16 * FS, XT = 16 * NW;
+  const int slim = SA ? g.M : g.N, xlim = SA ? g.N : g.M;
+  const int tiles_s = (slim + SR - 1) / SR, tiles_x = (xlim + XT - 1) / XT;
+  g.tiles_m = tiles_s;
+  const long long want = (PERSIST_TARGET + (long long)tiles_s * nbatch - 1) / ((long long)tiles_s * nbatch);
+  const int npersist = (int)(want < 1 ? 1 : (want > tiles_x ? tiles_x : want));
+  dim3 grid(tiles_s * npersist, nbatch, 1);
+  hipLaunchKernelGGL((k_stream1<PK, SA, SC, XC, FS, NW, KS, OutT>), grid, dim3(64 * NW), 0, st, g);
+  return hipGetLastError();
+}
+
 StreamArgs sdef() {
   StreamArgs g;
   std::memset(&g, 0, sizeof(g));
@@ -287,8 +300,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   {
     StageTimer tm(0, st);
     if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, false, 4, 2, 4, 112, false, double>(g, 1, st);
-    else if (prec == SB2_FP32) e = launch_s<PK_F32, true, true, false, 8, 2, 4, 112, false, float>(g, 1, st);
-    else e = launch_s<PK_H16, true, true, false, 8, 2, 4, 128, false, float>(g, 1, st);
+    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, false, 8, 4, 112, float>(g, 1, st);
+    else e = launch_s1<PK_H16, true, true, false, 8, 4, 128, float>(g, 1, st);
   }
   if (e != hipSuccess) return e;
 
@@ -302,8 +315,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   {
     StageTimer tm(1, st);
     if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, true, 7, 1, 4, 64, false, double>(g, ns * N, st);
-    else if (prec == SB2_FP32) e = launch_s<PK_F32, true, true, true, 7, 2, 4, 112, false, float>(g, ns * N, st);
-    else e = launch_s<PK_H16, true, true, true, 7, 2, 4, 128, false, float>(g, ns * N, st);
+    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, true, 7, 4, 112, float>(g, ns * N, st);
+    else e = launch_s1<PK_H16, true, true, true, 7, 4, 128, float>(g, ns * N, st);
   }
   if (e != hipSuccess) return e;
 
@@ -317,8 +330,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   {
     StageTimer tm(2, st);
     if (prec == SB2_FP64) e = launch_s<PK_F64, false, true, true, 7, 1, 4, 64, false, double>(g, ns, st);
-    else if (prec == SB2_FP32) e = launch_s<PK_F32, false, true, true, 7, 2, 4, 112, false, float>(g, ns, st);
-    else e = launch_s<PK_H16, false, true, true, 7, 2, 4, 128, false, float>(g, ns, st);
+    else if (prec == SB2_FP32) e = launch_s1<PK_F32, false, true, true, 7, 4, 112, float>(g, ns, st);
+    else e = launch_s1<PK_H16, false, true, true, 7, 4, 128, float>(g, ns, st);
   }
   if (e != hipSuccess) return e;
 

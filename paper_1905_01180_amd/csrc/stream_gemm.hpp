@@ -487,3 +487,339 @@ __global__ void __launch_bounds__(64 * NW) k_stream(const StreamArgs g) {
 }
 
 }  // namespace sb2
+
+namespace sb2 {
+
+// ---------------------------------------------------------------------------
+// Single-slab variant (K <= KS) with whole-tile register double buffering.
+// Each wave streams one 16-row fragment (FX = 1); all K-groups of its next
+// tile are loaded into a second register set while the current tile is
+// multiplied, so a wave keeps a full tile of loads in flight.  The shared
+// operand stays resident in LDS for the workgroup's whole walk over tiles.
+// ---------------------------------------------------------------------------
+template <int PK, bool XC, int KS>
+struct XTile {
+  using T = typename ST<PK>::T;
+  static constexpr int KV = ST<PK>::KV, NKG = KS / (4 * KV);
+  T re[NKG][KV];
+  T im[XC ? NKG : 1][KV];
+  hx8 ph[(PK == PK_H16 && !XC) ? NKG : 1], pl[(PK == PK_H16 && !XC) ? NKG : 1];
+};
+
+template <int PK, bool SA, bool SC, bool XC, int FS, int NW, int KS, typename OutT>
+__global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
+  using Tr = ST<PK>;
+  using T = typename Tr::T;
+  using LT = typename Tr::L;
+  using acc_t = typename Tr::acc;
+  using XT_ = XTile<PK, XC, KS>;
+  constexpr bool H = PK == PK_H16;
+  constexpr int KV = Tr::KV, KG = 4 * KV, NKG = KS / KG;
+  constexpr int NT = 64 * NW;
+  constexpr int SR = 16 * FS;
+  constexpr int XT = 16 * NW;
+  constexpr int NPL = (H ? 2 : 1) * (SC ? 2 : 1);
+  constexpr int LPB0 = KS * (int)sizeof(LT);
+  constexpr int PADB = ((16 - LPB0 % 128) + 128) % 128;
+  constexpr int LP = KS + PADB / (int)sizeof(LT);
+  constexpr int SE = SC ? 2 : 1, XE = XC ? 2 : 1;
+  static_assert(KS % KG == 0, "slab must hold whole K-groups");
+
+  __shared__ __attribute__((aligned(16))) LT sS[NPL][SR][LP];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int grp = lane >> 4, lr = lane & 15;
+  const int ts = blockIdx.x % g.tiles_m, pp = blockIdx.x / g.tiles_m;
+  const int npersist = (int)(gridDim.x / g.tiles_m);
+  const int s0 = ts * SR;
+  const int slim = SA ? g.M : g.N;
+  const int xlim = SA ? g.N : g.M;
+  const int tiles_x = (xlim + XT - 1) / XT;
+  const int bz = blockIdx.y, bh = bz / g.nbl, bl = bz - bh * g.nbl;
+  const int kbeg = 0, kend = g.K;
+  const i64 sbatch = (i64)bh * g.sSbh + (i64)bl * g.sSbl;
+  const i64 xbatch = (i64)bh * g.sXbh + (i64)bl * g.sXbl;
+  float ss = 1.f, sx = 1.f;
+  if constexpr (H) {
+    ss = split_scale(g.smax);
+    sx = split_scale(g.xmax);
+  }
+  OutT* Cb = reinterpret_cast<OutT*>(g.C) + 2 * ((i64)bh * g.sCbh + (i64)bl * g.sCbl);
+  const double unscale = H ? 1.0 / ((double)ss * (double)sx) : 1.0;
+  float mx = 0.f;
+
+  // ---- shared operand: staged once ----
+  {
+    const T* Sb = reinterpret_cast<const T*>(g.S) + SE * sbatch;
+    constexpr int ITEMS = SR * KS, PER = (ITEMS + NT - 1) / NT;
+    constexpr int BATCH = 8, NB = (PER + BATCH - 1) / BATCH;
+#pragma unroll 1
+    for (int bt = 0; bt < NB; ++bt) {
+      T re[BATCH], im[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int L = tid + (bt * BATCH + u) * NT;
+        const int r = L / KS, c = L - (L / KS) * KS;
+        const int srow = s0 + r, k = kbeg + c;
+        re[u] = T(0);
+        im[u] = T(0);
+        if (L < ITEMS && srow < slim && k < kend) {
+          const T* p = Sb + SE * ((i64)srow * g.sSs + k);
+          if constexpr (SC) {
+            typedef T t2 __attribute__((ext_vector_type(2)));
+            const t2 v = *reinterpret_cast<const t2*>(p);
+            re[u] = v[0];
+            im[u] = v[1];
+          } else {
+            re[u] = p[0];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int L = tid + (bt * BATCH + u) * NT;
+        if (L < ITEMS) {
+          const int r = L / KS, c = L - (L / KS) * KS;
+          if constexpr (H) {
+            split16(re[u] * ss, sS[0][r][c], sS[1][r][c]);
+            if constexpr (SC) split16(im[u] * ss, sS[2][r][c], sS[3][r][c]);
+          } else {
+            sS[0][r][c] = re[u];
+            if constexpr (SC) sS[1][r][c] = im[u];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- streamed tile loads (all K-groups) ----
+  // Rows past the end are clamped to the last row (a valid address) and their
+  // values zeroed; K-groups are either complete (no per-element test) or the
+  // single tail group, whose columns are clamped to K-1 and zeroed.
+  const char* Xb = reinterpret_cast<const char*>(g.X);
+  auto load_tile = [&](int tx, XT_& t) {
+    const int x = tx * XT + w * 16 + lr;
+    const bool xv = x < xlim;
+    const bool edge = tx * XT + XT > xlim;                  // uniform per workgroup
+    const int xc = xv ? x : xlim - 1;
+#pragma unroll
+    for (int q = 0; q < NKG; ++q) {
+      const int kg0 = kbeg + q * KG;
+      const int k = kg0 + KV * grp;
+      if constexpr (H && !XC) {
+        const _Float16* p = reinterpret_cast<const _Float16*>(Xb) + xbatch + (i64)xc * g.sXx;
+        hx8 vh, vl;
+        if (kg0 + KG <= kend) {
+          vh = *reinterpret_cast<const hx8*>(p + k);
+          vl = *reinterpret_cast<const hx8*>(p + g.sXplane + k);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int kk = min(k + e, kend - 1);
+            const bool ok = k + e < kend;
+            const _Float16 a = p[kk], b = p[g.sXplane + kk];
+            vh[e] = ok ? a : (_Float16)0.f;
+            vl[e] = ok ? b : (_Float16)0.f;
+          }
+        }
+        if (edge && !xv) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) { vh[e] = (_Float16)0.f; vl[e] = (_Float16)0.f; }
+        }
+        t.ph[q] = vh;
+        t.pl[q] = vl;
+      } else {
+        const T* p = reinterpret_cast<const T*>(Xb) + XE * (xbatch + (i64)xc * g.sXx);
+        if (kg0 + KG <= kend) {
+#pragma unroll
+          for (int e = 0; e < KV; ++e) {
+            if constexpr (XC) {
+              typedef T t2 __attribute__((ext_vector_type(2)));
+              const t2 v = *reinterpret_cast<const t2*>(p + 2 * (k + e));
+              t.re[q][e] = v[0];
+              t.im[q][e] = v[1];
+            } else {
+              t.re[q][e] = p[k + e];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < KV; ++e) {
+            const int kk = min(k + e, kend - 1);
+            const bool ok = k + e < kend;
+            if constexpr (XC) {
+              typedef T t2 __attribute__((ext_vector_type(2)));
+              const t2 v = *reinterpret_cast<const t2*>(p + 2 * kk);
+              t.re[q][e] = ok ? v[0] : T(0);
+              t.im[q][e] = ok ? v[1] : T(0);
+            } else {
+              const T v = p[kk];
+              t.re[q][e] = ok ? v : T(0);
+            }
+          }
+        }
+        if (edge && !xv) {
+#pragma unroll
+          for (int e = 0; e < KV; ++e) {
+            t.re[q][e] = T(0);
+            if constexpr (XC) t.im[q][e] = T(0);
+          }
+        }
+      }
+    }
+  };
+
+  // output offsets: the part that does not change from tile to tile
+  // SA: rows m = s0 + 16 i + fr(q) are fixed, columns n = x0 + lr move with the tile
+  // SB: columns n = s0 + 16 i + lr are fixed, rows m = x0 + fr(q) move with the tile
+  i64 fixoff[SA ? 4 : 1];
+  i64 fixstep = 0;                                          // per fragment i
+  if constexpr (SA) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fixoff[q] = (i64)(s0 + frag_row<T>(grp, q)) * g.sCm;
+    fixstep = (i64)16 * g.sCm;
+  } else {
+    fixoff[0] = (i64)(s0 + lr) * g.sCn;
+    fixstep = (i64)16 * g.sCn;
+  }
+
+  // ---- multiply one tile and write it out ----
+  auto do_tile = [&](int tx, const XT_& t) {
+    acc_t cr[FS], ci[FS];
+    zero_arr(cr);
+    zero_arr(ci);
+#pragma unroll
+    for (int q = 0; q < NKG; ++q) {
+      const int kl = q * KG;
+      if (kbeg + kl < kend) {
+        if constexpr (H) {
+          hx8 xrh, xrl, xih, xil;
+          if constexpr (XC) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float a = t.re[q][e] * sx, b = t.im[q][e] * sx;
+              const _Float16 ah = (_Float16)a, bh = (_Float16)b;
+              xrh[e] = ah;
+              xrl[e] = (_Float16)(a - (float)ah);
+              xih[e] = bh;
+              xil[e] = (_Float16)(b - (float)bh);
+            }
+          } else {
+            xrh = t.ph[q];
+            xrl = t.pl[q];
+            xih = xrh;
+            xil = xrl;
+          }
+#pragma unroll
+          for (int i = 0; i < FS; ++i) {
+            const int row = i * 16 + lr;
+            const hx8 srh = *reinterpret_cast<const hx8*>(&sS[0][row][kl + 8 * grp]);
+            const hx8 srl = *reinterpret_cast<const hx8*>(&sS[1][row][kl + 8 * grp]);
+            hx8 sih = srh, sil = srl;
+            if constexpr (SC) {
+              sih = *reinterpret_cast<const hx8*>(&sS[NPL - 2][row][kl + 8 * grp]);
+              sil = *reinterpret_cast<const hx8*>(&sS[NPL - 1][row][kl + 8 * grp]);
+            }
+            if constexpr (SA) cmac3<SC, XC>(cr[i], ci[i], srh, srl, sih, sil, xrh, xrl, xih, xil);
+            else cmac3<XC, SC>(cr[i], ci[i], xrh, xrl, xih, xil, srh, srl, sih, sil);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < FS; ++i) {
+            const int row = i * 16 + lr;
+            T sr[4], si[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              sr[e] = sS[0][row][kl + 4 * grp + e];
+              si[e] = SC ? sS[NPL - 1][row][kl + 4 * grp + e] : T(0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const T xre = t.re[q][e];
+              const T xim = XC ? t.im[q][e] : T(0);
+              if constexpr (SA) cmac<SC, XC>(cr[i], ci[i], sr[e], si[e], xre, xim);
+              else cmac<XC, SC>(cr[i], ci[i], xre, xim, sr[e], si[e]);
+            }
+          }
+        }
+      }
+    }
+    const int x0 = tx * XT + w * 16;
+    const T usc = (T)unscale;                                // a power of two: exact
+    // interior tiles (every row and column in range) store without per-element tests
+    const bool interior = (x0 + 16 <= xlim) && (s0 + SR <= slim);
+    if constexpr (SA) {
+      const int n = x0 + lr;
+      const i64 coff = (i64)n * g.sCn;
+      const bool nv = n < g.N;
+#pragma unroll
+      for (int i = 0; i < FS; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = s0 + i * 16 + frag_row<T>(grp, q);
+          if (interior || (nv && m < g.M)) {
+            typedef OutT o2 __attribute__((ext_vector_type(2)));
+            o2 v;
+            v[0] = (OutT)(cr[i][q] * usc);
+            v[1] = (OutT)(ci[i][q] * usc);
+            *reinterpret_cast<o2*>(Cb + 2 * (fixoff[q] + i * fixstep + coff)) = v;
+            if constexpr (H) mx = fmaxf(mx, fmaxf(fabsf((float)v[0]), fabsf((float)v[1])));
+          }
+        }
+      }
+    } else {
+      i64 roff[4];
+      bool rv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = x0 + frag_row<T>(grp, q);
+        rv[q] = m < g.M;
+        if (g.Mlo > 0) {
+          const int mh = m / g.Mlo;
+          roff[q] = (i64)mh * g.sCmh + (i64)(m - mh * g.Mlo) * g.sCm;
+        } else {
+          roff[q] = (i64)m * g.sCm;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < FS; ++i) {
+        const int n = s0 + i * 16 + lr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (interior || (rv[q] && n < g.N)) {
+            typedef OutT o2 __attribute__((ext_vector_type(2)));
+            o2 v;
+            v[0] = (OutT)(cr[i][q] * usc);
+            v[1] = (OutT)(ci[i][q] * usc);
+            *reinterpret_cast<o2*>(Cb + 2 * (roff[q] + fixoff[0] + i * fixstep)) = v;
+            if constexpr (H) mx = fmaxf(mx, fmaxf(fabsf((float)v[0]), fabsf((float)v[1])));
+          }
+        }
+      }
+    }
+  };
+
+  XT_ ta, tb;
+  int tx = pp;
+  if (tx < tiles_x) load_tile(tx, ta);
+  while (tx < tiles_x) {
+    int txn = tx + npersist;
+    if (txn < tiles_x) load_tile(txn, tb);
+    do_tile(tx, ta);
+    tx = txn;
+    if (tx >= tiles_x) break;
+    txn = tx + npersist;
+    if (txn < tiles_x) load_tile(txn, ta);
+    do_tile(tx, tb);
+    tx = txn;
+  }
+  if constexpr (H) {
+    if (g.cmax) {
+      mx = wave_max(mx);
+      if (lane == 0 && mx > 0.f) atomicMax(g.cmax, __float_as_uint(mx));
+    }
+  }
+}
+
+}  // namespace sb2
