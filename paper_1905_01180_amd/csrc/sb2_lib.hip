@@ -300,8 +300,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   {
     StageTimer tm(0, st);
     if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, false, 4, 2, 4, 112, false, double>(g, 1, st);
-    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, false, 8, 4, 112, float>(g, 1, st);
-    else e = launch_s1<PK_H16, true, true, false, 8, 4, 128, float>(g, 1, st);
+    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, false, 8, 8, 128, float>(g, 1, st);
+    else e = launch_s1<PK_H16, true, true, false, 8, 8, 128, float>(g, 1, st);
   }
   if (e != hipSuccess) return e;
 
@@ -315,8 +315,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   {
     StageTimer tm(1, st);
     if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, true, 7, 1, 4, 64, false, double>(g, ns * N, st);
-    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, true, 7, 4, 112, float>(g, ns * N, st);
-    else e = launch_s1<PK_H16, true, true, true, 7, 4, 128, float>(g, ns * N, st);
+    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, true, 7, 8, 128, float>(g, ns * N, st);
+    else e = launch_s1<PK_H16, true, true, true, 7, 8, 128, float>(g, ns * N, st);
   }
   if (e != hipSuccess) return e;
 
@@ -330,8 +330,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   {
     StageTimer tm(2, st);
     if (prec == SB2_FP64) e = launch_s<PK_F64, false, true, true, 7, 1, 4, 64, false, double>(g, ns, st);
-    else if (prec == SB2_FP32) e = launch_s1<PK_F32, false, true, true, 7, 4, 112, float>(g, ns, st);
-    else e = launch_s1<PK_H16, false, true, true, 7, 4, 128, float>(g, ns, st);
+    else if (prec == SB2_FP32) e = launch_s1<PK_F32, false, true, true, 7, 8, 128, float>(g, ns, st);
+    else e = launch_s1<PK_H16, false, true, true, 7, 8, 128, float>(g, ns, st);
   }
   if (e != hipSuccess) return e;
 

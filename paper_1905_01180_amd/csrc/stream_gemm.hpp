@@ -497,10 +497,10 @@ namespace sb2 {
 // multiplied, so a wave keeps a full tile of loads in flight.  The shared
 // operand stays resident in LDS for the workgroup's whole walk over tiles.
 // ---------------------------------------------------------------------------
-template <int PK, bool XC, int KS>
+template <int PK, bool XC, int NKG>
 struct XTile {
   using T = typename ST<PK>::T;
-  static constexpr int KV = ST<PK>::KV, NKG = KS / (4 * KV);
+  static constexpr int KV = ST<PK>::KV;
   T re[NKG][KV];
   T im[XC ? NKG : 1][KV];
   hx8 ph[(PK == PK_H16 && !XC) ? NKG : 1], pl[(PK == PK_H16 && !XC) ? NKG : 1];
@@ -512,9 +512,12 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
   using T = typename Tr::T;
   using LT = typename Tr::L;
   using acc_t = typename Tr::acc;
-  using XT_ = XTile<PK, XC, KS>;
   constexpr bool H = PK == PK_H16;
   constexpr int KV = Tr::KV, KG = 4 * KV, NKG = KS / KG;
+  // the streamed rows are buffered in two super-groups of SGQ K-groups each
+  constexpr int SGQ = NKG / 2;
+  static_assert(NKG % 2 == 0, "two super-groups per tile");
+  using XT_ = XTile<PK, XC, SGQ>;
   constexpr int NT = 64 * NW;
   constexpr int SR = 16 * FS;
   constexpr int XT = 16 * NW;
@@ -598,14 +601,15 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
   // values zeroed; K-groups are either complete (no per-element test) or the
   // single tail group, whose columns are clamped to K-1 and zeroed.
   const char* Xb = reinterpret_cast<const char*>(g.X);
-  auto load_tile = [&](int tx, XT_& t) {
+  auto load_sg = [&](int tx, int half, XT_& t) {
     const int x = tx * XT + w * 16 + lr;
     const bool xv = x < xlim;
     const bool edge = tx * XT + XT > xlim;                  // uniform per workgroup
     const int xc = xv ? x : xlim - 1;
 #pragma unroll
-    for (int q = 0; q < NKG; ++q) {
-      const int kg0 = kbeg + q * KG;
+    for (int q = 0; q < SGQ; ++q) {
+      const int kg0 = kbeg + (half * SGQ + q) * KG;
+      if (kg0 >= kend) continue;                            // uniform: whole group past K
       const int k = kg0 + KV * grp;
       if constexpr (H && !XC) {
         const _Float16* p = reinterpret_cast<const _Float16*>(Xb) + xbatch + (i64)xc * g.sXx;
@@ -684,14 +688,12 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
     fixstep = (i64)16 * g.sCn;
   }
 
-  // ---- multiply one tile and write it out ----
-  auto do_tile = [&](int tx, const XT_& t) {
-    acc_t cr[FS], ci[FS];
-    zero_arr(cr);
-    zero_arr(ci);
+  // ---- multiply one super-group into the accumulators ----
+  acc_t cr[FS], ci[FS];
+  auto compute_sg = [&](int half, const XT_& t) {
 #pragma unroll
-    for (int q = 0; q < NKG; ++q) {
-      const int kl = q * KG;
+    for (int q = 0; q < SGQ; ++q) {
+      const int kl = (half * SGQ + q) * KG;
       if (kbeg + kl < kend) {
         if constexpr (H) {
           hx8 xrh, xrl, xih, xil;
@@ -745,6 +747,10 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
         }
       }
     }
+  };
+
+  // ---- write one finished tile ----
+  auto epilogue = [&](int tx) {
     const int x0 = tx * XT + w * 16;
     const T usc = (T)unscale;                                // a power of two: exact
     // interior tiles (every row and column in range) store without per-element tests
@@ -800,19 +806,19 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
     }
   };
 
+  // super-group 0 of a tile lives in ta, super-group 1 in tb; each load is
+  // issued one super-group ahead of its use
   XT_ ta, tb;
   int tx = pp;
-  if (tx < tiles_x) load_tile(tx, ta);
-  while (tx < tiles_x) {
-    int txn = tx + npersist;
-    if (txn < tiles_x) load_tile(txn, tb);
-    do_tile(tx, ta);
-    tx = txn;
-    if (tx >= tiles_x) break;
-    txn = tx + npersist;
-    if (txn < tiles_x) load_tile(txn, ta);
-    do_tile(tx, tb);
-    tx = txn;
+  if (tx < tiles_x) load_sg(tx, 0, ta);
+  for (; tx < tiles_x; tx += npersist) {
+    zero_arr(cr);
+    zero_arr(ci);
+    load_sg(tx, 1, tb);
+    compute_sg(0, ta);
+    if (tx + npersist < tiles_x) load_sg(tx + npersist, 0, ta);
+    compute_sg(1, tb);
+    epilogue(tx);
   }
   if constexpr (H) {
     if (g.cmax) {
