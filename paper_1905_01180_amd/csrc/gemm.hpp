@@ -46,6 +46,7 @@ struct GemmArgs {
   const void* B; i64 sBk, sBn, sBbh, sBbl;
   void* C; i64 sCm, sCn, sCbh, sCbl, sCz;
   int Mlo; i64 sCmh;       // Mlo > 0: m = mh Mlo + ml addresses mh sCmh + ml sCm
+  int Klo; i64 sAkh, sBkh; // K2 kernels: k = kh Klo + kl addresses kh s*kh + kl s*k
   int conjA, conjB;
   double alpha_re, alpha_im;
   int beta1;               // accumulate into C instead of overwriting
@@ -113,8 +114,9 @@ struct TileRegs {
     else { c = L / R; r = L - c * R; }
   }
 
-  __device__ __forceinline__ void load(const T* __restrict__ base, i64 sr, i64 sc, int rlim, int clim,
-                                       bool cfast, int tid) {
+  template <class Off>
+  __device__ __forceinline__ void load(const T* __restrict__ base, Off off_of, int rlim, int clim, bool cfast,
+                                       int tid) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int L = tid + e * NT;
@@ -122,7 +124,7 @@ struct TileRegs {
       rc(L, cfast, r, c);
       const bool ok = (L < R * Cc) && r < rlim && c < clim;
       if (ok) {
-        const i64 off = (i64)r * sr + (i64)c * sc;
+        const i64 off = off_of(r, c);
         if constexpr (CPLX) {
           typedef T t2 __attribute__((ext_vector_type(2)));
           const t2 x = *reinterpret_cast<const t2*>(base + 2 * off);
@@ -136,6 +138,11 @@ struct TileRegs {
         if constexpr (CPLX) im[e] = T(0);
       }
     }
+  }
+
+  __device__ __forceinline__ void load(const T* __restrict__ base, i64 sr, i64 sc, int rlim, int clim,
+                                       bool cfast, int tid) {
+    load(base, [&](int r, int c) { return (i64)r * sr + (i64)c * sc; }, rlim, clim, cfast, tid);
   }
 };
 
@@ -199,7 +206,7 @@ __device__ __forceinline__ void store_elem(const GemmArgs& g, OutT* Cb, int m, i
 // ---------------------------------------------------------------------------
 // float64 / float32 kernel
 // ---------------------------------------------------------------------------
-template <typename T, typename OutT, int WM, int WN, int FM, int FN, bool AC, bool BC, bool ACC64>
+template <typename T, typename OutT, int WM, int WN, int FM, int FN, bool AC, bool BC, bool ACC64, bool K2 = false>
 __global__ void __launch_bounds__(64 * WM * WN)
 k_gemm(const GemmArgs g) {
   constexpr int NT = 64 * WM * WN;
@@ -233,8 +240,20 @@ k_gemm(const GemmArgs g) {
 
   auto gload = [&](int k0) {
     const int klim = kend - k0;
-    ra.load(Ab + PA * (i64)k0 * g.sAk, g.sAm, g.sAk, mlim, klim, a_cfast, tid);
-    rb.load(Bb + PB * (i64)k0 * g.sBk, g.sBk, g.sBn, klim, nlim, b_cfast, tid);
+    if constexpr (K2) {
+      // two-level K: element k = kh Klo + kl at kh s*kh + kl s*k
+      ra.load(Ab, [&](int r, int c) {
+        const int kk = k0 + c, kh = kk / g.Klo;
+        return (i64)r * g.sAm + (i64)kh * g.sAkh + (i64)(kk - kh * g.Klo) * g.sAk;
+      }, mlim, klim, a_cfast, tid);
+      rb.load(Bb, [&](int r, int c) {
+        const int kk = k0 + r, kh = kk / g.Klo;
+        return (i64)kh * g.sBkh + (i64)(kk - kh * g.Klo) * g.sBk + (i64)c * g.sBn;
+      }, klim, nlim, b_cfast, tid);
+    } else {
+      ra.load(Ab + PA * (i64)k0 * g.sAk, g.sAm, g.sAk, mlim, klim, a_cfast, tid);
+      rb.load(Bb + PB * (i64)k0 * g.sBk, g.sBk, g.sBn, klim, nlim, b_cfast, tid);
+    }
   };
   auto lstore = [&](int buf) {
 #pragma unroll

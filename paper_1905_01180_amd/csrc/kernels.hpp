@@ -58,9 +58,9 @@ __device__ __forceinline__ void block_atomic_max(float x, unsigned* dst) {
 constexpr int EXPM_THREADS = 1024;
 constexpr int EXPM_MAXN = 128;
 
-// C = A B (+ I if add_eye) scaled by `scale`; all N x N row-major complex.
-__device__ void wg_matmul(int N, const cplx* __restrict__ A, const cplx* __restrict__ B, cplx* __restrict__ C,
-                          double scale, bool add_eye) {
+// C = scale A B (+ I if add_eye) (+ C if accumulate); all N x N row-major complex.
+__device__ void wg_matmul(int N, const cplx* __restrict__ A, const cplx* __restrict__ B, cplx* C,
+                          double scale, bool add_eye, bool accumulate = false) {
   __shared__ cplx sa[EXPM_MAXN][17];
   __shared__ cplx sb[16][EXPM_MAXN + 1];
   const int t = threadIdx.x;
@@ -104,6 +104,7 @@ __device__ void wg_matmul(int N, const cplx* __restrict__ A, const cplx* __restr
       if (i < N && j < N) {
         cplx r = acc[a][b] * scale;
         if (add_eye && i == j) r[0] += 1.0;
+        if (accumulate) r += C[i * N + j];
         C[i * N + j] = r;
       }
     }
@@ -157,6 +158,82 @@ k_expm(int N, const cplx* __restrict__ H, double alpha_re, double alpha_im, cplx
     for (int e = t; e < N * N; e += EXPM_THREADS) E[e] = S[e];
     __syncthreads();
   }
+}
+
+// Frechet derivative of the exponential: Lout = L_exp(B, D) with
+// B = alpha op(H), op(H) = H or H^dag.  The pair (exp(X), L_exp(X, F)) is
+// carried through the same scaling, Taylor (Horner) and squaring steps as
+// k_expm: Horner on E <- I + X E / j gives L <- (F E + X L) / j, and a
+// squaring E <- E E gives L <- E L + L E (Higham, "Functions of Matrices",
+// Sec. 10.6; Al-Mohy & Higham 2009).  Scratch: 6 N^2 complex.
+__global__ void __launch_bounds__(EXPM_THREADS)
+k_expm_frechet(int N, const cplx* __restrict__ H, int dagger, double alpha_re, double alpha_im,
+               const cplx* __restrict__ D, cplx* __restrict__ Lout, cplx* __restrict__ scr) {
+  __shared__ double colsum[EXPM_MAXN];
+  __shared__ int s_sh;
+  const int t = threadIdx.x;
+  const int nn = N * N;
+  cplx* X = scr;
+  cplx* F = scr + nn;
+  cplx* E = scr + 2 * nn;
+  cplx* L = scr + 3 * nn;
+  cplx* T1 = scr + 4 * nn;
+  cplx* T2 = scr + 5 * nn;
+  const cplx alpha = mk(alpha_re, alpha_im);
+  for (int e = t; e < nn; e += EXPM_THREADS) {
+    const int i = e / N, j = e - (e / N) * N;
+    const cplx hv = dagger ? conj_(H[j * N + i]) : H[e];
+    X[e] = cmul(alpha, hv);
+  }
+  __syncthreads();
+  for (int j = t; j < N; j += EXPM_THREADS) {
+    double sum = 0;
+    for (int i = 0; i < N; ++i) {
+      const cplx x = X[i * N + j];
+      sum += sqrt(x[0] * x[0] + x[1] * x[1]);
+    }
+    colsum[j] = sum;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double nrm = 0;
+    for (int j = 0; j < N; ++j) nrm = fmax(nrm, colsum[j]);
+    int sq = 0;
+    while (nrm > 0.5 && sq < 1000) { nrm *= 0.5; ++sq; }
+    s_sh = sq;
+  }
+  __syncthreads();
+  const int sq = s_sh;
+  const double sc = ldexp(1.0, -sq);
+  for (int e = t; e < nn; e += EXPM_THREADS) {
+    const int i = e / N, j = e - (e / N) * N;
+    X[e] = X[e] * sc;
+    F[e] = D[e] * sc;
+    E[e] = mk(i == j ? 1.0 : 0.0, 0.0);
+    L[e] = mk(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 16; j >= 1; --j) {
+    wg_matmul(N, F, E, T1, 1.0 / j, false);
+    wg_matmul(N, X, L, T1, 1.0 / j, false, true);
+    wg_matmul(N, X, E, T2, 1.0 / j, true);
+    for (int e = t; e < nn; e += EXPM_THREADS) {
+      L[e] = T1[e];
+      E[e] = T2[e];
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < sq; ++q) {
+    wg_matmul(N, E, L, T1, 1.0, false);
+    wg_matmul(N, L, E, T1, 1.0, false, true);
+    wg_matmul(N, E, E, T2, 1.0, false);
+    for (int e = t; e < nn; e += EXPM_THREADS) {
+      L[e] = T1[e];
+      E[e] = T2[e];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < nn; e += EXPM_THREADS) Lout[e] = L[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -378,10 +455,88 @@ __global__ void k_rho_finish(int N, const cplx* __restrict__ Y, const cplx* __re
   out[e] = Y[e] - (a + b) * dt;
 }
 
+// x <- (a + i b) x
+__global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = cmul(mk(a, b), x[e]);
+}
+
 // Strided complex copy, used to lay out small operands.
 __global__ void k_copy(i64 n, const cplx* __restrict__ src, cplx* __restrict__ dst) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint helpers (float64)
+// ---------------------------------------------------------------------------
+
+// out[e] (+)= sum_z part[z count + e]
+__global__ void k_sum_partials(i64 count, int nz, const cplx* __restrict__ part, cplx* __restrict__ out,
+                               int accumulate) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  cplx acc = accumulate ? out[e] : mk(0, 0);
+  for (int z = 0; z < nz; ++z) acc += part[(i64)z * count + e];
+  out[e] = acc;
+}
+
+// slice cotangents of a chunk: gSs[b] = dL/dSigma of slice b, gSt[i][b][j] = gSs[b][i][j]
+__global__ void k_pack_gs(int N, int npairs, const cplx* __restrict__ gSl, const cplx* __restrict__ gSg,
+                          cplx* __restrict__ gSs, cplx* __restrict__ gSt) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2 * nn * npairs) return;
+  const i64 b = e / nn;
+  const int r = (int)(e - b * nn);
+  const int i = r / N, j = r - (r / N) * N;
+  const i64 kp = b >> 1;
+  const cplx x = (b & 1) ? gSg[kp * nn + r] : gSl[kp * nn + r];
+  gSs[e] = x;
+  gSt[(i64)i * (2 * npairs) * N + b * N + j] = x;
+}
+
+// chain cotangents of the slices back onto the GKBA functions of the chunk
+__global__ void k_scatter_gg(int N, int npairs, const cplx* __restrict__ gGs, const cplx* __restrict__ gGbs,
+                             cplx* __restrict__ gGl, cplx* __restrict__ gGg, cplx* __restrict__ gGlb,
+                             cplx* __restrict__ gGgb) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn * npairs) return;
+  const i64 kp = e / nn;
+  const i64 r = e - kp * nn;
+  gGl[e] = gGs[(2 * kp) * nn + r];
+  gGg[e] = gGs[(2 * kp + 1) * nn + r];
+  gGgb[e] += gGbs[(2 * kp) * nn + r];
+  gGlb[e] += gGbs[(2 * kp + 1) * nn + r];
+}
+
+// GKBA adjoint, elementwise part:
+//   gX = -i (gGl + gGg),  gY = -i (gGlb + gGgb),  gU = i gGg - i gGgb^dag
+__global__ void k_gkba_adj(int N, int T, const cplx* __restrict__ gGl, const cplx* __restrict__ gGg,
+                           const cplx* __restrict__ gGlb, const cplx* __restrict__ gGgb, cplx* __restrict__ gX,
+                           cplx* __restrict__ gY, cplx* __restrict__ gU) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn * T) return;
+  const i64 k = e / nn;
+  const int r = (int)(e - k * nn);
+  const int i = r / N, j = r - (r / N) * N;
+  gX[e] = times_mi(gGl[e] + gGg[e]);
+  gY[e] = times_mi(gGlb[e] + gGgb[e]);
+  const cplx gd = conj_(gGgb[k * nn + (i64)j * N + i]);
+  gU[e] = times_i(gGg[e]) - times_i(gd);
+}
+
+// gv_ijkl = 2 gw_ijkl - gw_jikl + gVp[i][(l,k,j)],  gw_mqsj = gWT[(j,s,q)][m]
+__global__ void k_assemble_gv(int N, const double* __restrict__ gWT, const double* __restrict__ gVp,
+                              double* __restrict__ gv) {
+  const i64 n = N, n3 = n * n * n;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3 * n) return;
+  const int l = (int)(e % n), k = (int)((e / n) % n), j = (int)((e / (n * n)) % n), i = (int)(e / n3);
+  const i64 lk = ((i64)l * N + k) * N;
+  gv[e] = 2.0 * gWT[(lk + j) * N + i] - gWT[(lk + i) * N + j] + gVp[(i64)i * n3 + lk + j];
 }
 
 }  // namespace sb2

@@ -108,13 +108,13 @@ void r4_split(int N, int ns, int prec, int& nz, int& kchunk) {
   nz = (int)((K + kc - 1) / kc);
 }
 
-ChainPlan chain_plan(int N, int pairs, int prec, size_t base) {
+ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0) {
   ChainPlan p;
   p.N = N;
   const size_t n4 = (size_t)N * N * N * N, n3 = (size_t)N * N * N, n2 = (size_t)N * N;
   const size_t bb = bulk_bytes(prec);
   const size_t per_pair = 2 * 2 * n4 * 2 * bb;      // two buffers x two slices x N^4 complex
-  size_t S = INTERMEDIATE_BUDGET / per_pair;
+  size_t S = forceS > 0 ? (size_t)forceS : INTERMEDIATE_BUDGET / per_pair;
   if (S < 1) S = 1;
   if (S > (size_t)pairs) S = pairs;
   const size_t smax = 65535 / (2 * (size_t)N);       // R2 batch = 2 S N workgroup rows in grid.y
@@ -277,7 +277,7 @@ StreamArgs sdef() {
   return g;
 }
 
-hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipStream_t st) {
+hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipStream_t st, void* cbuf = nullptr) {
   const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
   unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
   const void* Gs = at(ws, p.gs);
@@ -325,7 +325,8 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   g.M = (int)n3; g.N = N; g.K = N;
   g.X = X2; g.sXx = N; g.sXbh = n4;
   g.S = GbT; g.sSs = N; g.sSbh = n2;
-  g.C = X1; g.Mlo = N; g.sCmh = N; g.sCm = n3; g.sCn = 1; g.sCbh = n4;
+  void* Cout = cbuf ? cbuf : X1;
+  g.C = Cout; g.Mlo = N; g.sCmh = N; g.sCm = n3; g.sCn = 1; g.sCbh = n4;
   if (h16) { g.xmax = scal + S_BMAX; g.smax = scal + S_GBMAX; g.cmax = scal + S_CMAX; }
   {
     StageTimer tm(2, st);
@@ -339,7 +340,7 @@ hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipS
   g = sdef();
   g.M = N; g.N = ns * N; g.K = (int)n3; g.kchunk = p.kchunk;
   g.S = Vp; g.sSs = p.KpV; g.sSplane = (i64)N * p.KpV;
-  g.X = X1; g.sXx = n3;
+  g.X = Cout; g.sXx = n3;
   g.C = part; g.sCm = (i64)ns * N; g.sCn = 1; g.sCz = (i64)N * ns * N;
   if (h16) { g.smax = scal + S_VMAX; g.xmax = scal + S_CMAX; g.kpromote = 2; }
   {
@@ -432,6 +433,320 @@ hipError_t propagators(int N, int T, const void* h, double dt, cplx* U, cplx* ex
   return hipSuccess;
 }
 
+
+// Propagators and GKBA two-time functions for all past times (float64):
+// U[k] = exp(-i h (T-k) dt), X = U rho, Y = rho U^dag and the four G's.
+hipError_t gkba_history(int N, int T, const void* h, const void* rho_hist, double dt, cplx* U, cplx* X, cplx* Y,
+                        cplx* Gl, cplx* Gg, cplx* Glb, cplx* Ggb, cplx* ex1, cplx* ex2, hipStream_t s) {
+  StageTimer tm(5, s);
+  const i64 nn = (i64)N * N;
+  hipError_t e = propagators(N, T, h, dt, U, ex1, ex2, s);
+  if (e != hipSuccess) return e;
+  GemmArgs g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = U; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+  g.B = rho_hist; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+  g.C = X; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = rho_hist; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+  g.B = U; g.sBk = 1; g.sBn = N; g.sBbh = nn; g.conjB = 1;
+  g.C = Y; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gkba, dim3(blocks((long long)T * nn, 256)), dim3(256), 0, s, N, T, U, X, Y, Gl, Gg, Glb, Ggb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the collision integral (float64).  Per chunk of past times the
+// forward chain R1..R4 is recomputed (A', B and C kept), the slices' Sigma
+// cotangents are pulled back through R4..R1, and the cotangents of v (through
+// both Vp and W_T), of G and of Gbar are accumulated; then the GKBA functions,
+// the propagator powers and the exponential are differentiated in reverse.
+// ---------------------------------------------------------------------------
+struct BwdPlan {
+  CollPlan f;          // forward history arrays (U, X, Y, G's, Sigma's)
+  ChainPlan ch;        // chain buffers: W_T, Vp, Gs, GbT, A' (x1), B (x2), partials
+  size_t c3, gc, gb, gss, gst, ggs, ggbs, part2, gwt, gvp, gsl, gsg, ggl, ggg, gglb, gggb, gu, gu1, scr;
+  int nz2 = 1, kchunk2 = 16;
+  size_t end;
+};
+
+constexpr size_t BWD_BUDGET = 24ull << 30;   // five chain-sized float64 buffers
+
+BwdPlan bwd_plan(int N, int T) {
+  BwdPlan b;
+  b.f = coll_plan(N, T, SB2_FP64);
+  const size_t n2 = (size_t)N * N, n3 = n2 * N, n4 = n3 * N;
+  size_t S = BWD_BUDGET / (5 * 2 * n4 * C128);
+  if (S < 1) S = 1;
+  if (S > (size_t)T) S = T;
+  const size_t smax = 65535 / (2 * (size_t)N);
+  if (S > smax) S = smax;
+  size_t o = b.f.end;
+  b.ch = chain_plan(N, T, SB2_FP64, o, (int)S);
+  o = b.ch.end;
+  const size_t ns = 2 * S;
+  // split-K of the three K = N^3 reductions: >= ~1024 workgroups
+  const long long per_z = 2LL * (long long)ns;
+  long long nz = (1024 + per_z - 1) / per_z;
+  long long kc = ((long long)n3 + nz - 1) / nz;
+  kc = (kc + 15) / 16 * 16;
+  b.kchunk2 = (int)kc;
+  b.nz2 = (int)(((long long)n3 + kc - 1) / kc);
+  const size_t hist = (size_t)T * n2 * C128;
+  b.c3 = o; o += al(ns * n4 * C128);
+  b.gc = o; o += al(ns * n4 * C128);
+  b.gb = o; o += al(ns * n4 * C128);
+  b.gss = o; o += al(ns * n2 * C128);
+  b.gst = o; o += al(ns * n2 * C128);
+  b.ggs = o; o += al(ns * n2 * C128);
+  b.ggbs = o; o += al(ns * n2 * C128);
+  b.part2 = o; o += al((size_t)b.nz2 * ns * n2 * C128);
+  b.gwt = o; o += al(n3 * N * 8);
+  b.gvp = o; o += al(n4 * 8);
+  b.gsl = o; o += al(hist);
+  b.gsg = o; o += al(hist);
+  b.ggl = o; o += al(hist);
+  b.ggg = o; o += al(hist);
+  b.gglb = o; o += al(hist);
+  b.gggb = o; o += al(hist);
+  b.gu = o; o += al(hist);
+  b.gu1 = o; o += al(n2 * C128);
+  b.scr = o; o += al(6 * n2 * C128);
+  b.end = o;
+  return b;
+}
+
+// float64 GEMM configurations of the adjoint
+hipError_t zg_m(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 1, 4, 7, 1, true, true, false>(g, nb, s); }
+hipError_t zg_n(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 4, 1, 1, 7, true, true, false>(g, nb, s); }
+hipError_t zg_n_rc(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 4, 1, 1, 7, false, true, false>(g, nb, s); }
+hipError_t zg_m_cr(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 1, 4, 7, 1, true, false, false>(g, nb, s); }
+hipError_t zg_m_k2(GemmArgs g, int nb, hipStream_t s) {
+  constexpr int BM = 112, BN = 64;
+  if (g.kchunk <= 0) g.kchunk = g.K;
+  g.tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int nz = (g.K + g.kchunk - 1) / g.kchunk;
+  dim3 grid(g.tiles_m * tiles_n, nb, nz);
+  hipLaunchKernelGGL((k_gemm<double, double, 1, 4, 7, 1, true, true, false, true>), grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+#define BW_TRY(expr)                          \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return e_;          \
+  } while (0)
+
+hipError_t collision_backward(int N, int T, const double* v, const void* h, const void* rho, double dt,
+                              const void* gI, double* gv, void* gh, void* grho, const BwdPlan& b, void* ws,
+                              hipStream_t s) {
+  const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
+  cplx *U = P(b.f.U), *X = P(b.f.X), *Y = P(b.f.Y), *Gl = P(b.f.Gl), *Gg = P(b.f.Gg), *Glb = P(b.f.Glb),
+       *Ggb = P(b.f.Ggb), *Sl = P(b.f.Sl), *Sg = P(b.f.Sg);
+  cplx *gSl = P(b.gsl), *gSg = P(b.gsg), *gGl = P(b.ggl), *gGg = P(b.ggg), *gGlb = P(b.gglb), *gGgb = P(b.gggb),
+       *gU = P(b.gu), *gU1 = P(b.gu1);
+  const ChainPlan& ch = b.ch;
+  const cplx* Gs = P(ch.gs);
+  const cplx* GbT = P(ch.gbs);
+  cplx *A1 = P(ch.x1), *B2 = P(ch.x2), *C3 = P(b.c3), *GC = P(b.gc), *GB = P(b.gb);
+  cplx *gSs = P(b.gss), *gSt = P(b.gst), *gGs = P(b.ggs), *gGbs = P(b.ggbs), *part2 = P(b.part2);
+  double* gWT = reinterpret_cast<double*>(at(ws, b.gwt));
+  double* gVp = reinterpret_cast<double*>(at(ws, b.gvp));
+  const double* WT = reinterpret_cast<const double*>(at(ws, ch.w));
+  const double* Vp = reinterpret_cast<const double*>(at(ws, ch.vp));
+
+  BW_TRY(gkba_history(N, T, h, rho, dt, U, X, Y, Gl, Gg, Glb, Ggb, P(b.f.ex1), P(b.f.ex2), s));
+  BW_TRY(prep_dispatch(SB2_FP64, N, v, ch, ws, s));
+
+  // Sigma cotangents: I = dt sum_k (Sigma^>_k Glb_k - Sigma^<_k Ggb_k)
+  GemmArgs g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = gI; g.sAm = N; g.sAk = 1;
+  g.B = Glb; g.sBk = 1; g.sBn = N; g.sBbh = n2; g.conjB = 1;
+  g.C = gSg; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.alpha_re = dt;
+  BW_TRY(zgemm(g, T, s));
+  g.B = Ggb; g.C = gSl; g.alpha_re = -dt;
+  BW_TRY(zgemm(g, T, s));
+
+  const int S = ch.S;
+  for (int k0 = 0; k0 < T; k0 += S) {
+    const int np = T - k0 < S ? T - k0 : S;
+    const int ns = 2 * np;
+    const bool first = k0 == 0;
+    const i64 ko = (i64)k0 * n2;
+    // forward recompute of this chunk: A' (x1), B (x2), C (c3), Sigma
+    BW_TRY(pack_dispatch(SB2_FP64, N, np, Gl + ko, Gg + ko, Glb + ko, Ggb + ko, 0, ch, ws, s));
+    BW_TRY(run_chain(SB2_FP64, N, ns, ch, ws, s, C3));
+    hipLaunchKernelGGL(k_reduce_sigma, dim3(blocks(2LL * np * n2, 256)), dim3(256), 0, s, N, ns, ch.nz,
+                       reinterpret_cast<const cplx*>(at(ws, ch.part)), (i64)k0, Sl, Sg, (cplx*)nullptr,
+                       (cplx*)nullptr);
+    BW_TRY(hipGetLastError());
+    // Gbar cotangents from the collision terms: gGlb = dt Sg^H gI, gGgb = -dt Sl^H gI
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = Sg + ko; g.sAm = 1; g.sAk = N; g.sAbh = n2; g.conjA = 1;
+    g.B = gI; g.sBk = N; g.sBn = 1;
+    g.C = gGlb + ko; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.alpha_re = dt;
+    BW_TRY(zgemm(g, np, s));
+    g.A = Sl + ko; g.C = gGgb + ko; g.alpha_re = -dt;
+    BW_TRY(zgemm(g, np, s));
+    // slice cotangents
+    hipLaunchKernelGGL(k_pack_gs, dim3(blocks(2LL * np * n2, 256)), dim3(256), 0, s, N, np, gSl + ko, gSg + ko, gSs,
+                       gSt);
+    BW_TRY(hipGetLastError());
+    // R4 adjoint: gCt[b][(n,p)][j][r] = sum_i Vp[i][(n,p,r)] gS_b[i][j]
+    g = gdef();
+    g.M = (int)n3; g.N = N; g.K = N;
+    g.A = Vp; g.sAm = 1; g.sAk = ch.KpV;
+    g.B = gSs; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+    g.C = GC; g.Mlo = N; g.sCmh = n2; g.sCm = 1; g.sCn = N; g.sCbh = n4;
+    BW_TRY(zg_n_rc(g, ns, s));
+    // gVp[i][col] (+)= Re sum_{(b,j)} gS_b[i][j] conj(C_b[j][col])
+    g = gdef();
+    g.M = N; g.N = (int)n3; g.K = ns * N;
+    g.A = gSt; g.sAm = (i64)ns * N; g.sAk = 1;
+    g.B = C3; g.sBk = n3; g.sBn = 1; g.conjB = 1;
+    g.C = gVp; g.sCm = n3; g.sCn = 1; g.out_real = 1; g.beta1 = first ? 0 : 1;
+    BW_TRY(zg_m(g, 1, s));
+    // R3 adjoint: gB[b][(n,p,j)][s] = sum_r gCt[b][(n,p,j)][r] conj(GbT[b][r][s])
+    g = gdef();
+    g.M = (int)n3; g.N = N; g.K = N;
+    g.A = GC; g.sAm = N; g.sAk = 1; g.sAbh = n4;
+    g.B = GbT; g.sBk = N; g.sBn = 1; g.sBbh = n2; g.conjB = 1;
+    g.C = GB; g.sCm = N; g.sCn = 1; g.sCbh = n4;
+    BW_TRY(zg_n(g, ns, s));
+    // gGbar_b[s][r] = sum_{(n,p,j)} conj(B_b[(n,p,j)][s]) gCt_b[(n,p,j)][r]   (split-K)
+    g = gdef();
+    g.M = N; g.N = N; g.K = (int)n3; g.kchunk = b.kchunk2;
+    g.A = B2; g.sAm = 1; g.sAk = N; g.sAbh = n4; g.conjA = 1;
+    g.B = GC; g.sBk = N; g.sBn = 1; g.sBbh = n4;
+    g.C = part2; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.sCz = (i64)ns * n2;
+    BW_TRY(zg_m(g, ns, s));
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks((long long)ns * n2, 256)), dim3(256), 0, s, (i64)ns * n2,
+                       b.nz2, part2, gGbs, 0);
+    BW_TRY(hipGetLastError());
+    // R2 adjoint: gA'[b][n][x][q] = sum_p gB[b][n][p][x] conj(G_b[p][q])   (into GC)
+    g = gdef();
+    g.M = (int)n2; g.N = N; g.K = N; g.nbl = N;
+    g.A = GB; g.sAm = 1; g.sAk = n2; g.sAbh = n4; g.sAbl = n3;
+    g.B = Gs; g.sBk = N; g.sBn = 1; g.sBbh = n2; g.sBbl = 0; g.conjB = 1;
+    g.C = GC; g.sCm = N; g.sCn = 1; g.sCbh = n4; g.sCbl = n3;
+    BW_TRY(zg_n(g, ns * N, s));
+    // gG_b[p][q] = sum_{(n,x)} gB[b][n][p][x] conj(A'[b][n][x][q])   (second G slot, split-K)
+    g = gdef();
+    g.M = N; g.N = N; g.K = (int)n3; g.kchunk = b.kchunk2; g.Klo = (int)n2;
+    g.A = GB; g.sAm = n2; g.sAk = 1; g.sAkh = n3; g.sAbh = n4;
+    g.B = A1; g.sBk = N; g.sBkh = n3; g.sBn = 1; g.sBbh = n4; g.conjB = 1;
+    g.C = part2; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.sCz = (i64)ns * n2;
+    BW_TRY(zg_m_k2(g, ns, s));
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks((long long)ns * n2, 256)), dim3(256), 0, s, (i64)ns * n2,
+                       b.nz2, part2, gGs, 0);
+    BW_TRY(hipGetLastError());
+    // gG_b[n][m] += sum_col gA'[b][n][col] W_T[col][m]   (first G slot, split-K)
+    g = gdef();
+    g.M = N; g.N = N; g.K = (int)n3; g.kchunk = b.kchunk2;
+    g.A = GC; g.sAm = n3; g.sAk = 1; g.sAbh = n4;
+    g.B = WT; g.sBk = ch.KpW; g.sBn = 1;
+    g.C = part2; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.sCz = (i64)ns * n2;
+    BW_TRY(zg_m_cr(g, ns, s));
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks((long long)ns * n2, 256)), dim3(256), 0, s, (i64)ns * n2,
+                       b.nz2, part2, gGs, 1);
+    BW_TRY(hipGetLastError());
+    // gWT[col][m] (+)= Re sum_{(b,n)} gA'[(b,n)][col] conj(G[(b,n)][m])
+    g = gdef();
+    g.M = (int)n3; g.N = N; g.K = ns * N;
+    g.A = GC; g.sAm = 1; g.sAk = n3;
+    g.B = Gs; g.sBk = N; g.sBn = 1; g.conjB = 1;
+    g.C = gWT; g.sCm = N; g.sCn = 1; g.out_real = 1; g.beta1 = first ? 0 : 1;
+    BW_TRY(zg_n(g, 1, s));
+    hipLaunchKernelGGL(k_scatter_gg, dim3(blocks((long long)np * n2, 256)), dim3(256), 0, s, N, np, gGs, gGbs,
+                       gGl + ko, gGg + ko, gGlb + ko, gGgb + ko);
+    BW_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_assemble_gv, dim3(blocks(n4, 256)), dim3(256), 0, s, N, gWT, gVp, gv);
+  BW_TRY(hipGetLastError());
+
+  // GKBA adjoint: gX = -i(gGl + gGg), gY = -i(gGlb + gGgb), gU = i gGg - i gGgb^dag  (gX, gY reuse X, Y)
+  hipLaunchKernelGGL(k_gkba_adj, dim3(blocks((long long)T * n2, 256)), dim3(256), 0, s, N, T, gGl, gGg, gGlb, gGgb,
+                     X, Y, gU);
+  BW_TRY(hipGetLastError());
+  cplx* gX = X;
+  cplx* gY = Y;
+  // gU += gX rho^H + gY^H rho
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = gX; g.sAm = N; g.sAk = 1; g.sAbh = n2;
+  g.B = rho; g.sBk = 1; g.sBn = N; g.sBbh = n2; g.conjB = 1;
+  g.C = gU; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.beta1 = 1;
+  BW_TRY(zgemm(g, T, s));
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = gY; g.sAm = 1; g.sAk = N; g.sAbh = n2; g.conjA = 1;
+  g.B = rho; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+  g.C = gU; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.beta1 = 1;
+  BW_TRY(zgemm(g, T, s));
+  // grho = U^H gX + gY U
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = U; g.sAm = 1; g.sAk = N; g.sAbh = n2; g.conjA = 1;
+  g.B = gX; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+  g.C = grho; g.sCm = N; g.sCn = 1; g.sCbh = n2;
+  BW_TRY(zgemm(g, T, s));
+  g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = gY; g.sAm = N; g.sAk = 1; g.sAbh = n2;
+  g.B = U; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+  g.C = grho; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.beta1 = 1;
+  BW_TRY(zgemm(g, T, s));
+
+  // powers: U[k] = P_m, m = T - k, P_m = U1 P_{m-1}.  Reverse sweep m = T..2:
+  //   gU1 += gP_m P_{m-1}^H,  gP_{m-1} += U1^H gP_m;  finally gU1 += gP_1.
+  const cplx* U1 = U + (i64)(T - 1) * n2;
+  hipLaunchKernelGGL(k_copy, dim3(blocks(n2, 256)), dim3(256), 0, s, (i64)n2, gU + (i64)(T - 1) * n2, gU1);
+  BW_TRY(hipGetLastError());
+  for (int m = T; m >= 2; --m) {
+    const i64 km = (i64)(T - m) * n2, km1 = (i64)(T - m + 1) * n2;
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = gU + km; g.sAm = N; g.sAk = 1;
+    g.B = U + km1; g.sBk = 1; g.sBn = N; g.conjB = 1;
+    g.C = gU1; g.sCm = N; g.sCn = 1; g.beta1 = 1;
+    BW_TRY(zgemm(g, 1, s));
+    if (m - 1 >= 2) {
+      g = gdef();
+      g.M = N; g.N = N; g.K = N;
+      g.A = U1; g.sAm = 1; g.sAk = N; g.conjA = 1;
+      g.B = gU + km; g.sBk = N; g.sBn = 1;
+      g.C = gU + km1; g.sCm = N; g.sCn = 1; g.beta1 = 1;
+      BW_TRY(zgemm(g, 1, s));
+    }
+  }
+  // gP_1 for m = 1 is gU[T-1] plus the chain's contributions accumulated above (when T >= 2 the
+  // m = 2 step folded U1^H gP_2 into gU[T-1] only if it was applied; do it here instead)
+  if (T >= 2) {
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = U1; g.sAm = 1; g.sAk = N; g.conjA = 1;
+    g.B = gU + (i64)(T - 2) * n2; g.sBk = N; g.sBn = 1;
+    g.C = gU1; g.sCm = N; g.sCn = 1; g.beta1 = 1;
+    BW_TRY(zgemm(g, 1, s));
+  }
+  // U1 = exp(A), A = -i dt h:  gA = L_exp(A^H, gU1),  gh = i dt gA
+  hipLaunchKernelGGL(k_expm_frechet, dim3(1), dim3(EXPM_THREADS), 0, s, N, reinterpret_cast<const cplx*>(h), 1, 0.0,
+                     dt, gU1, reinterpret_cast<cplx*>(gh), P(b.scr));
+  BW_TRY(hipGetLastError());
+  // gh <- i dt gA  (scale in place)
+  g = gdef();
+  (void)g;
+  hipLaunchKernelGGL(k_scale_c, dim3(blocks(n2, 256)), dim3(256), 0, s, (i64)n2, reinterpret_cast<cplx*>(gh), 0.0, dt);
+  return hipGetLastError();
+}
+
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 }  // namespace
@@ -487,6 +802,9 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
       return coll_plan(N, T, prec).end;
     case SB2_OP_RHO_STEP:
       return rho_plan(N);
+    case SB2_OP_COLLISION_BACKWARD:
+      if (T < 1 || T > SB2_MAX_T || prec != SB2_FP64) return 0;
+      return bwd_plan(N, T).end;
     default:
       return 0;
   }
@@ -602,11 +920,15 @@ int sb2_rho_step(int N, const void* h, const void* rho, const void* I, double dt
 int sb2_collision_backward(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
                            const void* gI, double* gv, void* gh, void* grho, int prec, void* ws,
                            size_t ws_bytes, void* stream) {
-  (void)v; (void)h; (void)rho_hist; (void)gI; (void)gv; (void)gh; (void)grho; (void)ws; (void)ws_bytes;
-  (void)stream; (void)dt;
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !gI || !gv || !gh || !grho || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  if (!prec_ok(prec)) return SB2_EINVAL;
   if (prec != SB2_FP64) return SB2_EUNSUPPORTED;
-  return SB2_EUNSUPPORTED;
+  const BwdPlan b = bwd_plan(N, T);
+  if (ws_bytes < b.end) return SB2_EWORKSPACE;
+  hipError_t e = collision_backward(N, T, v, h, rho_hist, dt, gI, gv, gh, grho, b, ws,
+                                    reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SB2_OK : SB2_EHIP;
 }
 
 size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec) {

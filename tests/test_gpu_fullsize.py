@@ -1,0 +1,63 @@
+"""Full-size parity: the HIP path at the workloads' real shapes against the
+stored FP64 oracle values (tests/golden/oracle_c*.npz, written by
+tests/golden/make_golden.py from the oracle alone).
+
+Bars: float64 to 1e-11 (relative Frobenius error); float32 and split-float16
+to 1e-6 on I and on the sampled self-energies (the precision target of the
+reduced-precision paths).  Also checks particle-number conservation
+tr(I + I^dag) = 0, which holds at any size.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1905_01180_amd import inputs as gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+BAR = {"fp64": 1e-11, "fp32": 1e-6, "fp16x3": 1e-6}
+
+
+def rel_f(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _run(cid, prec):
+    path = os.path.join(GOLDEN, f"oracle_c{cid}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle values for config {cid} not generated")
+    from paper_1905_01180_amd import _lib
+    z = np.load(path)
+    s = gen.make_config(cid)
+    print(f"case: config {cid} N={s.n} T={s.t} {prec}", flush=True)
+    dev = torch.device("cuda")
+    got, sig = _lib.sb2_collision(torch.from_numpy(s.v).to(dev), torch.from_numpy(s.h).to(dev),
+                                  torch.from_numpy(s.rho_hist).to(dev), s.dt, prec, return_sigma=True)
+    got = got.cpu().numpy()
+    ks = z["sigma_ks"]
+    sl = sig[0, torch.as_tensor(ks, device=dev)].cpu().numpy()
+    sg = sig[1, torch.as_tensor(ks, device=dev)].cpu().numpy()
+    del sig
+    e_i = rel_f(got, z["i_ns"])
+    e_s = max(max(rel_f(sl[i], z["sigma_less"][i]), rel_f(sg[i], z["sigma_great"][i])) for i in range(len(ks)))
+    tr = abs(np.trace(got + got.conj().T)) / np.abs(got).sum()
+    print(f"config {cid} {prec}: rel_F(I) = {e_i:.3e}, max rel_F(Sigma) = {e_s:.3e}, |tr(I+I^dag)|/sum|I| = {tr:.1e}",
+          flush=True)
+    return e_i, e_s, tr
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_config1_full(prec):
+    e_i, e_s, tr = _run(1, prec)
+    assert e_i < BAR[prec] and e_s < BAR[prec]
+    assert tr < (1e-13 if prec == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
+def test_config2_full(prec):
+    e_i, e_s, tr = _run(2, prec)
+    assert e_i < BAR[prec] and e_s < BAR[prec]
+    assert tr < 1e-7
