@@ -21,7 +21,7 @@
 #include <vector>
 
 #include "kernels.hpp"
-#include "stream_gemm.hpp"
+#include "chain.hpp"
 #include "sb2.h"
 
 using namespace sb2;
@@ -33,7 +33,6 @@ inline size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 constexpr size_t C128 = 16;                       // bytes of one complex float64
 constexpr size_t INTERMEDIATE_BUDGET = 32ull << 30;  // bytes for the two chain intermediates
 
-enum ScaleWord { S_GMAX = 0, S_GBMAX, S_WMAX, S_VMAX, S_AMAX, S_BMAX, S_CMAX, S_NWORDS };
 
 inline bool prec_ok(int p) { return p == SB2_FP64 || p == SB2_FP32 || p == SB2_SPLIT_FP16; }
 inline size_t bulk_bytes(int p) { return p == SB2_FP64 ? 8 : 4; }   // one real scalar of the bulk type
@@ -238,118 +237,54 @@ hipError_t prep_interaction(int N, const double* v, const ChainPlan& p, void* ws
 
 constexpr int PERSIST_TARGET = 768;   // workgroups per launch when shared tiles stay resident
 
-template <int PK, bool SA, bool SC, bool XC, int FS, int FX, int NW, int KS, bool ACC64, typename OutT>
-hipError_t launch_s(StreamArgs g, int nbatch, hipStream_t st) {
-  constexpr int SR = 16 * FS, XT = 16 * FX * NW;
-  if (g.kchunk <= 0) g.kchunk = g.K > 0 ? g.K : 1;
-  const int slim = SA ? g.M : g.N, xlim = SA ? g.N : g.M;
-  const int tiles_s = (slim + SR - 1) / SR, tiles_x = (xlim + XT - 1) / XT;
-  g.tiles_m = tiles_s;
-  int npersist = tiles_x;
-  if (g.kchunk <= KS) {
-    const long long want = (PERSIST_TARGET + (long long)tiles_s * nbatch - 1) / ((long long)tiles_s * nbatch);
-    npersist = (int)(want < 1 ? 1 : (want > tiles_x ? tiles_x : want));
-  }
-  const int nz = g.K > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
-  dim3 grid(tiles_s * npersist, nbatch, nz);
-  hipLaunchKernelGGL((k_stream<PK, SA, SC, XC, FS, FX, NW, KS, ACC64, OutT>), grid, dim3(64 * NW), 0, st, g);
+int g_persist_target = PERSIST_TARGET;   // autotuner-chosen default (see sb2_autotune)
+
+ChainRefs chain_refs(int prec, int N, int ns, const ChainPlan& p, void* ws, void* cbuf) {
+  ChainRefs r;
+  r.N = N;
+  r.ns = ns;
+  r.prec = prec;
+  r.kchunk = p.kchunk;
+  r.KpW = p.KpW;
+  r.KpV = p.KpV;
+  r.Gs = at(ws, p.gs);
+  r.GbT = at(ws, p.gbs);
+  r.W = at(ws, p.w);
+  r.Vp = at(ws, p.vp);
+  r.X1 = at(ws, p.x1);
+  r.X2 = at(ws, p.x2);
+  r.C3 = cbuf;
+  r.part = at(ws, p.part);
+  r.scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
+  return r;
+}
+
+template <int PK, int STAGE>
+hipError_t launch_stage(const ChainRefs& r, hipStream_t st) {
+  int nbatch;
+  StreamArgs g = stage_args(STAGE, r, nbatch);
+  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, g_persist_target);
+  const long long gx = (long long)q.tiles_s * q.npersist;
+  dim3 grid((unsigned)gx, (unsigned)q.nbatch, (unsigned)q.nz);
+  StageTimer tm(STAGE, st);
+  hipLaunchKernelGGL((k_stage<PK, STAGE>), grid, dim3(64 * StageCfg<PK, STAGE>::NW), 0, st, g, q);
   return hipGetLastError();
 }
 
-template <int PK, bool SA, bool SC, bool XC, int FS, int NW, int KS, typename OutT>
-hipError_t launch_s1(StreamArgs g, int nbatch, hipStream_t st) {
-  constexpr int SR = 16 * FS, XT = 16 * NW;
-  const int slim = SA ? g.M : g.N, xlim = SA ? g.N : g.M;
-  const int tiles_s = (slim + SR - 1) / SR, tiles_x = (xlim + XT - 1) / XT;
-  g.tiles_m = tiles_s;
-  const long long want = (PERSIST_TARGET + (long long)tiles_s * nbatch - 1) / ((long long)tiles_s * nbatch);
-  const int npersist = (int)(want < 1 ? 1 : (want > tiles_x ? tiles_x : want));
-  dim3 grid(tiles_s * npersist, nbatch, 1);
-  hipLaunchKernelGGL((k_stream1<PK, SA, SC, XC, FS, NW, KS, OutT>), grid, dim3(64 * NW), 0, st, g);
-  return hipGetLastError();
-}
-
-StreamArgs sdef() {
-  StreamArgs g;
-  std::memset(&g, 0, sizeof(g));
-  g.nbl = 1;
-  g.kpromote = 4;
-  return g;
+template <int PK>
+hipError_t run_chain_pk(const ChainRefs& r, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_stage<PK, 0>(r, st)) != hipSuccess) return e;
+  if ((e = launch_stage<PK, 1>(r, st)) != hipSuccess) return e;
+  if ((e = launch_stage<PK, 2>(r, st)) != hipSuccess) return e;
+  return launch_stage<PK, 3>(r, st);
 }
 
 hipError_t run_chain(int prec, int N, int ns, const ChainPlan& p, void* ws, hipStream_t st, void* cbuf = nullptr) {
-  const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
-  unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
-  const void* Gs = at(ws, p.gs);
-  const void* GbT = at(ws, p.gbs);
-  const void* W = at(ws, p.w);
-  const void* Vp = at(ws, p.vp);
-  void* X1 = at(ws, p.x1);
-  void* X2 = at(ws, p.x2);
-  void* part = at(ws, p.part);
-  const bool h16 = prec == SB2_SPLIT_FP16;
-  hipError_t e;
-
-  // R1: A[(b,n)][x] = sum_m G[(b,n)][m] W_T[x][m], x = (j,s,q)
-  StreamArgs g = sdef();
-  g.M = ns * N; g.N = (int)n3; g.K = N;
-  g.S = Gs; g.sSs = N;
-  g.X = W; g.sXx = p.KpW; g.sXplane = n3 * p.KpW;
-  g.C = X1; g.sCm = n3; g.sCn = 1;
-  if (h16) { g.smax = scal + S_GMAX; g.xmax = scal + S_WMAX; g.cmax = scal + S_AMAX; }
-  {
-    StageTimer tm(0, st);
-    if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, false, 4, 2, 4, 112, false, double>(g, 1, st);
-    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, false, 8, 8, 128, float>(g, 1, st);
-    else e = launch_s1<PK_H16, true, true, false, 8, 8, 128, float>(g, 1, st);
-  }
-  if (e != hipSuccess) return e;
-
-  // R2: B[b][n][p][x] = sum_q G_b[p][q] A[b][n][x][q], x = (j,s); batch (b, n)
-  g = sdef();
-  g.M = N; g.N = (int)n2; g.K = N; g.nbl = N;
-  g.S = Gs; g.sSs = N; g.sSbh = n2; g.sSbl = 0;
-  g.X = X1; g.sXx = N; g.sXbh = n4; g.sXbl = n3;
-  g.C = X2; g.sCm = n2; g.sCn = 1; g.sCbh = n4; g.sCbl = n3;
-  if (h16) { g.smax = scal + S_GMAX; g.xmax = scal + S_AMAX; g.cmax = scal + S_BMAX; }
-  {
-    StageTimer tm(1, st);
-    if (prec == SB2_FP64) e = launch_s<PK_F64, true, true, true, 7, 1, 4, 64, false, double>(g, ns * N, st);
-    else if (prec == SB2_FP32) e = launch_s1<PK_F32, true, true, true, 7, 8, 128, float>(g, ns * N, st);
-    else e = launch_s1<PK_H16, true, true, true, 7, 8, 128, float>(g, ns * N, st);
-  }
-  if (e != hipSuccess) return e;
-
-  // R3: C[b][j][n][p][r] = sum_s B[b][(n,p,j)][s] GbT[b][r][s]; streamed rows (n,p,j)
-  g = sdef();
-  g.M = (int)n3; g.N = N; g.K = N;
-  g.X = X2; g.sXx = N; g.sXbh = n4;
-  g.S = GbT; g.sSs = N; g.sSbh = n2;
-  void* Cout = cbuf ? cbuf : X1;
-  g.C = Cout; g.Mlo = N; g.sCmh = N; g.sCm = n3; g.sCn = 1; g.sCbh = n4;
-  if (h16) { g.xmax = scal + S_BMAX; g.smax = scal + S_GBMAX; g.cmax = scal + S_CMAX; }
-  {
-    StageTimer tm(2, st);
-    if (prec == SB2_FP64) e = launch_s<PK_F64, false, true, true, 7, 1, 4, 64, false, double>(g, ns, st);
-    else if (prec == SB2_FP32) e = launch_s1<PK_F32, false, true, true, 7, 8, 128, float>(g, ns, st);
-    else e = launch_s1<PK_H16, false, true, true, 7, 8, 128, float>(g, ns, st);
-  }
-  if (e != hipSuccess) return e;
-
-  // R4: part[z][i][x] = sum_{k in chunk z} Vp[i][k] C[x][k], x = b N + j, k = (n,p,r)
-  g = sdef();
-  g.M = N; g.N = ns * N; g.K = (int)n3; g.kchunk = p.kchunk;
-  g.S = Vp; g.sSs = p.KpV; g.sSplane = (i64)N * p.KpV;
-  g.X = Cout; g.sXx = n3;
-  g.C = part; g.sCm = (i64)ns * N; g.sCn = 1; g.sCz = (i64)N * ns * N;
-  if (h16) { g.smax = scal + S_VMAX; g.xmax = scal + S_CMAX; g.kpromote = 2; }
-  {
-    StageTimer tm(3, st);
-    if (prec == SB2_FP64) e = launch_s<PK_F64, true, false, true, 7, 1, 4, 32, false, double>(g, 1, st);
-    else if (prec == SB2_FP32) e = launch_s<PK_F32, true, false, true, 7, 1, 4, 64, true, double>(g, 1, st);
-    else e = launch_s<PK_H16, true, false, true, 7, 1, 4, 128, true, double>(g, 1, st);
-  }
-  return e;
+  const ChainRefs r = chain_refs(prec, N, ns, p, ws, cbuf);
+  if (prec == SB2_FP64) return run_chain_pk<PK_F64>(r, st);
+  if (prec == SB2_FP32) return run_chain_pk<PK_F32>(r, st);
+  return run_chain_pk<PK_H16>(r, st);
 }
 
 template <typename T>

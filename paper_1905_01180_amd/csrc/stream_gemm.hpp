@@ -105,7 +105,7 @@ __device__ __forceinline__ void split16(float x, _Float16& hi, _Float16& lo) {
 //   streamed tile while walking K slabs (multi-slab / split-K case);
 //   grid.y = batch, grid.z = split-K chunk.
 template <int PK, bool SA, bool SC, bool XC, int FS, int FX, int NW, int KS, bool ACC64, typename OutT>
-__global__ void __launch_bounds__(64 * NW) k_stream(const StreamArgs g) {
+__device__ __forceinline__ void stream_body(const StreamArgs& g, int bx, int by, int bzz, int npersist_arg) {
   using Tr = ST<PK>;
   using T = typename Tr::T;
   using LT = typename Tr::L;
@@ -126,16 +126,16 @@ __global__ void __launch_bounds__(64 * NW) k_stream(const StreamArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int grp = lane >> 4, lr = lane & 15;
-  const int ts = blockIdx.x % g.tiles_m, pp = blockIdx.x / g.tiles_m;   // tiles_m = shared tiles
+  const int ts = bx % g.tiles_m, pp = bx / g.tiles_m;   // tiles_m = shared tiles
   const int s0 = ts * SR;
   const int slim = SA ? g.M : g.N;
   const int xlim = SA ? g.N : g.M;
   const int tiles_x = (xlim + XT - 1) / XT;
-  const int bz = blockIdx.y, bh = bz / g.nbl, bl = bz - bh * g.nbl;
-  const int kbeg = blockIdx.z * g.kchunk;
+  const int bz = by, bh = bz / g.nbl, bl = bz - bh * g.nbl;
+  const int kbeg = bzz * g.kchunk;
   const int kend = min(g.K, kbeg + g.kchunk);
   const bool single = kend - kbeg <= KS;
-  const int npersist = (int)(gridDim.x / g.tiles_m);
+  const int npersist = npersist_arg;
 
   const i64 sbatch = (i64)bh * g.sSbh + (i64)bl * g.sSbl;
   const i64 xbatch = (i64)bh * g.sXbh + (i64)bl * g.sXbl;
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(64 * NW) k_stream(const StreamArgs g) {
     ss = split_scale(g.smax);
     sx = split_scale(g.xmax);
   }
-  OutT* Cb = reinterpret_cast<OutT*>(g.C) + 2 * ((i64)bh * g.sCbh + (i64)bl * g.sCbl + (i64)blockIdx.z * g.sCz);
+  OutT* Cb = reinterpret_cast<OutT*>(g.C) + 2 * ((i64)bh * g.sCbh + (i64)bl * g.sCbl + (i64)bzz * g.sCz);
   const double unscale = H ? 1.0 / ((double)ss * (double)sx) : 1.0;
 
   acc_t cr[FS][FX], ci[FS][FX];
@@ -486,6 +486,13 @@ __global__ void __launch_bounds__(64 * NW) k_stream(const StreamArgs g) {
   }
 }
 
+template <int PK, bool SA, bool SC, bool XC, int FS, int FX, int NW, int KS, bool ACC64, typename OutT>
+__global__ void __launch_bounds__(64 * NW) k_stream(const StreamArgs g) {
+  stream_body<PK, SA, SC, XC, FS, FX, NW, KS, ACC64, OutT>(g, blockIdx.x, blockIdx.y, blockIdx.z,
+                                                            (int)(gridDim.x / g.tiles_m));
+}
+
+
 }  // namespace sb2
 
 namespace sb2 {
@@ -507,7 +514,7 @@ struct XTile {
 };
 
 template <int PK, bool SA, bool SC, bool XC, int FS, int NW, int KS, typename OutT>
-__global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
+__device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by, int npersist) {
   using Tr = ST<PK>;
   using T = typename Tr::T;
   using LT = typename Tr::L;
@@ -532,13 +539,12 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int grp = lane >> 4, lr = lane & 15;
-  const int ts = blockIdx.x % g.tiles_m, pp = blockIdx.x / g.tiles_m;
-  const int npersist = (int)(gridDim.x / g.tiles_m);
+  const int ts = bx % g.tiles_m, pp = bx / g.tiles_m;
   const int s0 = ts * SR;
   const int slim = SA ? g.M : g.N;
   const int xlim = SA ? g.N : g.M;
   const int tiles_x = (xlim + XT - 1) / XT;
-  const int bz = blockIdx.y, bh = bz / g.nbl, bl = bz - bh * g.nbl;
+  const int bz = by, bh = bz / g.nbl, bl = bz - bh * g.nbl;
   const int kbeg = 0, kend = g.K;
   const i64 sbatch = (i64)bh * g.sSbh + (i64)bl * g.sSbl;
   const i64 xbatch = (i64)bh * g.sXbh + (i64)bl * g.sXbl;
@@ -827,5 +833,11 @@ __global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
     }
   }
 }
+
+template <int PK, bool SA, bool SC, bool XC, int FS, int NW, int KS, typename OutT>
+__global__ void __launch_bounds__(64 * NW) k_stream1(const StreamArgs g) {
+  stream1_body<PK, SA, SC, XC, FS, NW, KS, OutT>(g, blockIdx.x, blockIdx.y, (int)(gridDim.x / g.tiles_m));
+}
+
 
 }  // namespace sb2
