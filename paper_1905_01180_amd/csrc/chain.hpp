@@ -171,4 +171,16 @@ k_stage_group(const ChainRefs* __restrict__ refs, const GroupTable t) {
   run_stage_block<PK, STAGE>(g, q, b - t.off[i]);
 }
 
+// Write a table of chain refs into device memory (the table travels as kernel
+// arguments, so the sequence stays valid under stream capture).
+constexpr int REFS_PER_WRITE = 24;
+struct RefsChunk {
+  int count;
+  ChainRefs r[REFS_PER_WRITE];
+};
+__global__ void k_write_refs(ChainRefs* __restrict__ dst, const RefsChunk c) {
+  const int i = threadIdx.x;
+  if (i < c.count) dst[i] = c.r[i];
+}
+
 }  // namespace sb2

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
 #include <vector>
 
 #include "kernels.hpp"
@@ -142,7 +143,7 @@ struct CollPlan {
   size_t end;
 };
 
-CollPlan coll_plan(int N, int T, int prec) {
+CollPlan coll_plan(int N, int T, int prec, int forceS = 0) {
   CollPlan c;
   const size_t hist = (size_t)T * N * N * C128;
   size_t o = 0;
@@ -158,7 +159,7 @@ CollPlan coll_plan(int N, int T, int prec) {
   c.terms = o; o += al(hist);
   c.ex1 = o; o += al((size_t)N * N * C128);
   c.ex2 = o; o += al((size_t)N * N * C128);
-  c.ch = chain_plan(N, T, prec, o);
+  c.ch = chain_plan(N, T, prec, o, forceS);
   c.end = c.ch.end;
   return c;
 }
@@ -682,6 +683,165 @@ hipError_t collision_backward(int N, int T, const double* v, const void* h, cons
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Batched evaluation of several systems.  All systems advance in R common
+// rounds (system b takes S_b = ceil(T_b / R) past times per round, R as small
+// as the intermediate budget allows); in every round each chain stage is ONE
+// grouped launch over all systems that still have past times left.  The
+// per-system set-up (interaction layout, propagators, GKBA functions) and the
+// collision sums are per-system launches around the rounds.
+// ---------------------------------------------------------------------------
+constexpr size_t BATCH_BUDGET = 48ull << 30;
+
+struct BatchPlan {
+  int rounds = 1;
+  std::vector<CollPlan> cp;
+  std::vector<size_t> base;
+  size_t refs = 0;     // device ChainRefs table
+  size_t end = 0;
+};
+
+BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
+  BatchPlan bp;
+  const size_t bb = bulk_bytes(prec);
+  int R = 1;
+  for (;; ++R) {
+    size_t tot = 0;
+    bool fits_grid = true;
+    for (int b = 0; b < nsys; ++b) {
+      const size_t n4 = (size_t)sys[b].N * sys[b].N * sys[b].N * sys[b].N;
+      const size_t S = ((size_t)sys[b].T + R - 1) / R;
+      tot += S * 2 * 2 * n4 * 2 * bb;
+      if (S > 65535 / (2 * (size_t)sys[b].N)) fits_grid = false;
+    }
+    if ((tot <= BATCH_BUDGET && fits_grid) || R >= SB2_MAX_T) break;
+  }
+  bp.rounds = R;
+  size_t o = 0;
+  bp.refs = o;
+  o += al(sizeof(ChainRefs) * MAX_GROUP);
+  for (int b = 0; b < nsys; ++b) {
+    const int S = (sys[b].T + R - 1) / R;
+    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S));
+    bp.base.push_back(o);
+    o += bp.cp.back().end;
+  }
+  bp.end = o;
+  return bp;
+}
+
+template <int PK, int STAGE>
+hipError_t launch_group(const std::vector<ChainRefs>& refs, const ChainRefs* d_refs, hipStream_t st) {
+  GroupTable t;
+  t.count = (int)refs.size();
+  t.persist_target = g_persist_target;
+  long long off = 0;
+  for (int i = 0; i < t.count; ++i) {
+    t.off[i] = off;
+    int nbatch;
+    StreamArgs g = stage_args(STAGE, refs[i], nbatch);
+    off += stage_geom<PK, STAGE>(g, nbatch, t.persist_target).blocks();
+  }
+  t.off[t.count] = off;
+  if (off <= 0) return hipSuccess;
+  StageTimer tm(STAGE, st);
+  hipLaunchKernelGGL((k_stage_group<PK, STAGE>), dim3((unsigned)off), dim3(64 * StageCfg<PK, STAGE>::NW), 0, st,
+                     d_refs, t);
+  return hipGetLastError();
+}
+
+template <int PK>
+hipError_t group_chain(const std::vector<ChainRefs>& refs, const ChainRefs* d, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_group<PK, 0>(refs, d, st)) != hipSuccess) return e;
+  if ((e = launch_group<PK, 1>(refs, d, st)) != hipSuccess) return e;
+  if ((e = launch_group<PK, 2>(refs, d, st)) != hipSuccess) return e;
+  return launch_group<PK, 3>(refs, d, st);
+}
+
+hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const BatchPlan& bp, void* ws,
+                             hipStream_t s) {
+  hipError_t e;
+  std::vector<char*> wsb(nsys);
+  for (int b = 0; b < nsys; ++b) wsb[b] = reinterpret_cast<char*>(ws) + bp.base[b];
+  // per-system set-up: interaction layouts, propagators and GKBA functions
+  for (int b = 0; b < nsys; ++b) {
+    const CollPlan& c = bp.cp[b];
+    void* w = wsb[b];
+    auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(w, off)); };
+    if ((e = gkba_history(sys[b].N, sys[b].T, sys[b].h, sys[b].rho_hist, sys[b].dt, P(c.U), P(c.X), P(c.Y), P(c.Gl),
+                          P(c.Gg), P(c.Glb), P(c.Ggb), P(c.ex1), P(c.ex2), s)) != hipSuccess)
+      return e;
+    if ((e = prep_dispatch(prec, sys[b].N, sys[b].v, c.ch, w, s)) != hipSuccess) return e;
+  }
+  ChainRefs* d_refs = reinterpret_cast<ChainRefs*>(at(ws, bp.refs));
+  for (int r = 0; r < bp.rounds; ++r) {
+    std::vector<ChainRefs> refs;
+    std::vector<int> who, kk0, nps;
+    for (int b = 0; b < nsys; ++b) {
+      const CollPlan& c = bp.cp[b];
+      const int k0 = r * c.ch.S;
+      if (k0 >= sys[b].T) continue;
+      const int np = sys[b].T - k0 < c.ch.S ? sys[b].T - k0 : c.ch.S;
+      const int N = sys[b].N;
+      const size_t o = (size_t)k0 * N * N * C128;
+      void* w = wsb[b];
+      if ((e = pack_dispatch(prec, N, np, at(w, c.Gl + o), at(w, c.Gg + o), at(w, c.Glb + o), at(w, c.Ggb + o), 0,
+                             c.ch, w, s)) != hipSuccess)
+        return e;
+      refs.push_back(chain_refs(prec, N, 2 * np, c.ch, w, nullptr));
+      who.push_back(b);
+      kk0.push_back(k0);
+      nps.push_back(np);
+    }
+    if (refs.empty()) break;
+    for (size_t i0 = 0; i0 < refs.size(); i0 += REFS_PER_WRITE) {
+      RefsChunk ck;
+      ck.count = (int)std::min(refs.size() - i0, (size_t)REFS_PER_WRITE);
+      for (int i = 0; i < ck.count; ++i) ck.r[i] = refs[i0 + i];
+      hipLaunchKernelGGL(k_write_refs, dim3(1), dim3(64), 0, s, d_refs + i0, ck);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (prec == SB2_FP64) e = group_chain<PK_F64>(refs, d_refs, s);
+    else if (prec == SB2_FP32) e = group_chain<PK_F32>(refs, d_refs, s);
+    else e = group_chain<PK_H16>(refs, d_refs, s);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < refs.size(); ++i) {
+      const int b = who[i];
+      const CollPlan& c = bp.cp[b];
+      const int N = sys[b].N;
+      void* w = wsb[b];
+      StageTimer tm(6, s);
+      hipLaunchKernelGGL(k_reduce_sigma, dim3(blocks(2LL * nps[i] * N * N, 256)), dim3(256), 0, s, N, 2 * nps[i],
+                         c.ch.nz, reinterpret_cast<const cplx*>(at(w, c.ch.part)), (i64)kk0[i],
+                         reinterpret_cast<cplx*>(at(w, c.Sl)), reinterpret_cast<cplx*>(at(w, c.Sg)), (cplx*)nullptr,
+                         (cplx*)nullptr);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  // collision sums per system
+  for (int b = 0; b < nsys; ++b) {
+    const CollPlan& c = bp.cp[b];
+    const int N = sys[b].N, T = sys[b].T;
+    const i64 nn = (i64)N * N;
+    void* w = wsb[b];
+    auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(w, off)); };
+    StageTimer tm(7, s);
+    GemmArgs g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = P(c.Sg); g.sAm = N; g.sAk = 1; g.sAbh = nn;
+    g.B = P(c.Glb); g.sBk = N; g.sBn = 1; g.sBbh = nn;
+    g.C = P(c.terms); g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+    g.A = P(c.Sl); g.B = P(c.Ggb); g.alpha_re = -1.0; g.beta1 = 1;
+    if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, P(c.terms), sys[b].dt,
+                       reinterpret_cast<cplx*>(sys[b].I_out));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 }  // namespace
@@ -867,34 +1027,24 @@ int sb2_collision_backward(int N, int T, const double* v, const void* h, const v
 }
 
 size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec) {
-  if (nsys < 1 || !sys || !prec_ok(prec)) return 0;
-  size_t tot = 0;
-  for (int b = 0; b < nsys; ++b) {
-    const size_t w = sb2_workspace_size(SB2_OP_COLLISION, sys[b].N, sys[b].T, prec);
-    if (w == 0) return 0;
-    tot += w;
-  }
-  return tot;
+  if (nsys < 1 || nsys > MAX_GROUP || !sys || !prec_ok(prec)) return 0;
+  for (int i = 0; i < nsys; ++i)
+    if (sys[i].N < 1 || sys[i].N > SB2_MAX_N || sys[i].T < 1 || sys[i].T > SB2_MAX_T) return 0;
+  return batch_plan(nsys, sys, prec).end;
 }
 
 int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, size_t ws_bytes, void* stream) {
   if (nsys < 1 || !sys || !ws || !prec_ok(prec)) return SB2_EINVAL;
+  if (nsys > MAX_GROUP) return SB2_ESHAPE;
   for (int b = 0; b < nsys; ++b) {
     const sb2_system& q = sys[b];
     if (q.N < 1 || q.N > SB2_MAX_N || q.T < 1 || q.T > SB2_MAX_T) return SB2_ESHAPE;
     if (!q.v || !q.h || !q.rho_hist || !q.I_out || !finite_pos(q.dt)) return SB2_EINVAL;
   }
-  if (ws_bytes < sb2_batched_workspace_size(nsys, sys, prec)) return SB2_EWORKSPACE;
-  size_t off = 0;
-  for (int b = 0; b < nsys; ++b) {
-    const sb2_system& q = sys[b];
-    const size_t w = sb2_workspace_size(SB2_OP_COLLISION, q.N, q.T, prec);
-    const int st = sb2_collision(q.N, q.T, q.v, q.h, q.rho_hist, q.dt, q.I_out, nullptr, prec,
-                                 at(ws, off), w, stream);
-    if (st != SB2_OK) return st;
-    off += w;
-  }
-  return SB2_OK;
+  const BatchPlan bp = batch_plan(nsys, sys, prec);
+  if (ws_bytes < bp.end) return SB2_EWORKSPACE;
+  hipError_t e = collision_batched(nsys, sys, prec, bp, ws, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SB2_OK : SB2_EHIP;
 }
 
 }  // extern "C"
