@@ -66,7 +66,8 @@ typedef enum {
   SB2_OP_SIGMA = 0,
   SB2_OP_COLLISION = 1,
   SB2_OP_COLLISION_BACKWARD = 2,
-  SB2_OP_RHO_STEP = 3
+  SB2_OP_RHO_STEP = 3,
+  SB2_OP_AUTOTUNE = 4
 } sb2_op;
 
 /* Largest basis size and history length accepted. */
@@ -152,11 +153,38 @@ int sb2_rho_step(int N, const void* h, const void* rho, const void* I, double dt
 
 /* Workspace bytes for op (an sb2_op) at basis size N, history length T
  * (T = number of pairs B for SB2_OP_SIGMA, ignored for SB2_OP_RHO_STEP) and
- * precision prec.  Returns 0 for invalid arguments.                         */
+ * precision prec.  Returns 0 for invalid arguments.  The sizes do not depend
+ * on tuned launch parameters.                                               */
 size_t sb2_workspace_size(int op, int N, int T, int prec);
 
 /* Static description of a status code. */
 const char* sb2_status_string(int status);
+
+/* sb2_autotune -- choose launch parameters for basis size N and precision
+ * prec by timing sb2_collision on the first chunk of past times of the given
+ * workload (v, h, rho_hist, dt as for sb2_collision; the chunk is the number
+ * of past times one pass of the contraction chain holds).  ws must hold
+ * sb2_workspace_size(SB2_OP_AUTOTUNE, N, T, prec) bytes; its contents are
+ * scratch.  Searched, one after the other: the number of workgroups of the
+ * single-slab contraction launches (256 .. 3072, default 768), the split-K
+ * factor of the last contraction (50 .. 200 % of the default count) and, for
+ * SB2_SPLIT_FP16 with N <= 112, the number of workgroups of the fused second
+ * and third contraction (256 .. 2048, default 512).  The winner goes into a
+ * process-wide table (not thread-safe) consulted by every later call with
+ * this (N, prec), and to *persist_out / *r4pct_out / *fused_out when
+ * non-NULL.  Synchronises the stream: not for use under stream capture.  The
+ * workspace sizes of the other operations do not depend on tuned values.
+ * On error the previous entry for (N, prec) is restored.                    */
+int sb2_autotune(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, int prec,
+                 void* ws, size_t ws_bytes, void* stream, int* persist_out, int* r4pct_out, int* fused_out);
+
+/* sb2_set_tuning -- install launch parameters for (N, prec), e.g. values an
+ * earlier sb2_autotune returned: persist >= 1, 10 <= r4pct <= 200,
+ * fused_wgs >= 0 (0 runs the second and third contraction as two separate
+ * launches, which is also what every case other than SB2_SPLIT_FP16 with
+ * N <= 112 does); otherwise SB2_EINVAL.  Results do not depend on these values
+ * beyond the order of float32 accumulation.                                  */
+int sb2_set_tuning(int N, int prec, int persist, int r4pct, int fused_wgs);
 
 /* Stage timing for measurement (not for use under stream capture).
  * sb2_profile_enable(1) makes later calls bracket each stage launch with HIP

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsb2.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2}
-OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3}
+OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4}
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
           -5: "SB2_EUNSUPPORTED"}
 
@@ -64,6 +64,11 @@ def lib() -> ctypes.CDLL:
         L.sb2_collision_batched.argtypes = [_i, ctypes.POINTER(SystemDesc), _i, _vp, _sz, _vp]
         L.sb2_batched_workspace_size.restype = _sz
         L.sb2_batched_workspace_size.argtypes = [_i, ctypes.POINTER(SystemDesc), _i]
+        L.sb2_autotune.restype = _i
+        L.sb2_autotune.argtypes = [_i, _i, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp, ctypes.POINTER(_i),
+                                   ctypes.POINTER(_i), ctypes.POINTER(_i)]
+        L.sb2_set_tuning.restype = _i
+        L.sb2_set_tuning.argtypes = [_i, _i, _i, _i, _i]
         L.sb2_rho_step.restype = _i
         L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
         _lib = L
@@ -212,3 +217,30 @@ def sb2_collision_batched(systems, prec="fp16x3"):
     ws = workspace(nbytes, dev)
     _call("sb2_collision_batched", len(systems), arr, p, ws.data_ptr(), ws.numel(), _stream(dev))
     return outs
+
+
+def sb2_autotune(v, h, rho_hist, dt, prec="fp16x3"):
+    """Tune the launch parameters for (N, prec) on this workload's first chunk.
+
+    Returns {"persist": workgroups per single-slab launch, "r4pct": split-K
+    factor of the last contraction in percent, "fused": workgroups of the fused
+    second/third contraction (0 = separate launches)}; the library keeps the
+    values for later calls in this process."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    p = _prec(prec)
+    ws = workspace(sb2_workspace_size("autotune", n, t, p), v.device)
+    persist, r4pct, fused = _i(0), _i(0), _i(0)
+    _call("sb2_autotune", n, t, v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt), p, ws.data_ptr(),
+          ws.numel(), _stream(v.device), ctypes.byref(persist), ctypes.byref(r4pct), ctypes.byref(fused))
+    return {"persist": persist.value, "r4pct": r4pct.value, "fused": fused.value}
+
+
+DEFAULT_TUNING = {"persist": 768, "r4pct": 100, "fused": 512}
+
+
+def sb2_set_tuning(n: int, prec, persist: int = 768, r4pct: int = 100, fused: int = 512):
+    """Install launch parameters for (n, prec), e.g. from an earlier sb2_autotune."""
+    _call("sb2_set_tuning", n, _prec(prec), persist, r4pct, fused)

@@ -154,7 +154,7 @@ constexpr int MAX_GROUP = 64;
 
 struct GroupTable {
   int count;
-  int persist_target;
+  int persist[MAX_GROUP];     // per-member workgroup target of single-slab stages
   long long off[MAX_GROUP + 1];
 };
 
@@ -167,7 +167,7 @@ k_stage_group(const ChainRefs* __restrict__ refs, const GroupTable t) {
   const ChainRefs r = refs[i];
   int nbatch;
   StreamArgs g = stage_args(STAGE, r, nbatch);
-  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, t.persist_target);
+  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, t.persist[i]);
   run_stage_block<PK, STAGE>(g, q, b - t.off[i]);
 }
 

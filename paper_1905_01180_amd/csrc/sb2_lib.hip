@@ -19,10 +19,12 @@
 #include <cstdint>
 #include <cstring>
 #include <algorithm>
+#include <map>
 #include <vector>
 
 #include "kernels.hpp"
 #include "chain.hpp"
+#include "sandwich.hpp"
 #include "sb2.h"
 
 using namespace sb2;
@@ -81,6 +83,22 @@ hipError_t zgemm(GemmArgs g, int nbatch, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Workspace plans
+constexpr int PERSIST_TARGET = 768;   // default workgroups per single-slab stage launch
+
+constexpr int R23_WGS = 512;          // default workgroups of the fused second/third contraction
+constexpr int R23_MAX_N = 112;        // largest N of the fused kernel (LDS holds Gbar and one A slab)
+
+// Autotuned launch parameters per (N, precision): workgroups per single-slab
+// stage launch, the R4 split-K factor (percent of the default count) and the
+// workgroups of the fused R2+R3 kernel (split float16, N <= 112; 0 = run R2
+// and R3 as separate stages).
+struct TuneCfg { int persist = PERSIST_TARGET; int r4pct = 100; int r23 = R23_WGS; };
+std::map<std::pair<int, int>, TuneCfg> g_tune;
+TuneCfg tune_of(int N, int prec) {
+  auto it = g_tune.find({N, prec});
+  return it == g_tune.end() ? TuneCfg() : it->second;
+}
+
 // ---------------------------------------------------------------------------
 struct ChainPlan {
   int N = 0, S = 0, nz = 1, kchunk = 1;
@@ -91,13 +109,15 @@ struct ChainPlan {
 inline int slab_depth(int prec) { return prec == SB2_SPLIT_FP16 ? 128 : prec == SB2_FP32 ? 64 : 32; }
 inline size_t inter_bytes(int prec) { return prec == SB2_SPLIT_FP16 ? 4 : bulk_bytes(prec); }  // W_T / Vp per element
 
-// R4 split-K: enough workgroups to fill the chip, chunk a multiple of the slab depth.
-void r4_split(int N, int ns, int prec, int& nz, int& kchunk) {
+// R4 split-K: about 2048 * scale workgroups (enough to fill the chip at scale
+// 1), chunk a multiple of the slab depth.
+void r4_split(int N, int ns, int prec, int& nz, int& kchunk, double scale = 1.0) {
   const long long K = (long long)N * N * N;
   const int bk = slab_depth(prec);
   const long long coltiles = ((long long)ns * N + 63) / 64;
   const long long rowtiles = (N + 111) / 112;
-  long long want = (2048 + coltiles * rowtiles - 1) / (coltiles * rowtiles);
+  const long long target = (long long)(2048.0 * scale + 0.5);
+  long long want = (target + coltiles * rowtiles - 1) / (coltiles * rowtiles);
   const long long maxz = (K + bk - 1) / bk;
   if (want < 1) want = 1;
   if (want > maxz) want = maxz;
@@ -108,7 +128,9 @@ void r4_split(int N, int ns, int prec, int& nz, int& kchunk) {
   nz = (int)((K + kc - 1) / kc);
 }
 
-ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0) {
+// share: this chain's part of a grouped launch (1 when it runs alone); scales
+// the R4 split so that the whole launch, not each member, fills the chip.
+ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0, double share = 1.0) {
   ChainPlan p;
   p.N = N;
   const size_t n4 = (size_t)N * N * N * N, n3 = (size_t)N * N * N, n2 = (size_t)N * N;
@@ -122,7 +144,10 @@ ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0) {
   p.S = (int)S;
   p.KpW = (N + 7) / 8 * 8;
   p.KpV = ((i64)n3 + 7) / 8 * 8;
-  r4_split(N, 2 * p.S, prec, p.nz, p.kchunk);
+  int nz_max, kc_max;
+  r4_split(N, 2 * p.S, prec, nz_max, kc_max, 2.0);
+  r4_split(N, 2 * p.S, prec, p.nz, p.kchunk, tune_of(N, prec).r4pct / 100.0 * share);
+  if (p.nz > nz_max) nz_max = p.nz;
   const size_t ib = inter_bytes(prec);
   size_t o = base;
   p.scal = o; o += al(S_NWORDS * 4);
@@ -132,7 +157,7 @@ ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0) {
   p.gbs = o; o += al(2 * S * n2 * 2 * bb);
   p.x1 = o; o += al(2 * S * n4 * 2 * bb);
   p.x2 = o; o += al(2 * S * n4 * 2 * bb);
-  p.part = o; o += al((size_t)p.nz * N * 2 * S * N * C128);
+  p.part = o; o += al((size_t)nz_max * N * 2 * S * N * C128);
   p.end = o;
   return p;
 }
@@ -143,7 +168,7 @@ struct CollPlan {
   size_t end;
 };
 
-CollPlan coll_plan(int N, int T, int prec, int forceS = 0) {
+CollPlan coll_plan(int N, int T, int prec, int forceS = 0, double share = 1.0) {
   CollPlan c;
   const size_t hist = (size_t)T * N * N * C128;
   size_t o = 0;
@@ -159,9 +184,19 @@ CollPlan coll_plan(int N, int T, int prec, int forceS = 0) {
   c.terms = o; o += al(hist);
   c.ex1 = o; o += al((size_t)N * N * C128);
   c.ex2 = o; o += al((size_t)N * N * C128);
-  c.ch = chain_plan(N, T, prec, o, forceS);
+  c.ch = chain_plan(N, T, prec, o, forceS, share);
   c.end = c.ch.end;
   return c;
+}
+
+// Autotuning workload: the first chunk of past times (at most S), and its
+// workspace: that evaluation's plus one N x N output at the end.
+int tune_len(int N, int T, int prec) {
+  const int S = coll_plan(N, T, prec).ch.S;
+  return S < T ? S : T;
+}
+size_t tune_bytes(int N, int T, int prec) {
+  return al(coll_plan(N, tune_len(N, T, prec), prec).end) + al((size_t)N * N * C128);
 }
 
 size_t rho_plan(int N) { return 4 * al((size_t)N * N * C128); }
@@ -236,10 +271,6 @@ hipError_t prep_interaction(int N, const double* v, const ChainPlan& p, void* ws
   return hipGetLastError();
 }
 
-constexpr int PERSIST_TARGET = 768;   // workgroups per launch when shared tiles stay resident
-
-int g_persist_target = PERSIST_TARGET;   // autotuner-chosen default (see sb2_autotune)
-
 ChainRefs chain_refs(int prec, int N, int ns, const ChainPlan& p, void* ws, void* cbuf) {
   ChainRefs r;
   r.N = N;
@@ -264,7 +295,7 @@ template <int PK, int STAGE>
 hipError_t launch_stage(const ChainRefs& r, hipStream_t st) {
   int nbatch;
   StreamArgs g = stage_args(STAGE, r, nbatch);
-  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, g_persist_target);
+  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, tune_of(r.N, r.prec).persist);
   const long long gx = (long long)q.tiles_s * q.npersist;
   dim3 grid((unsigned)gx, (unsigned)q.nbatch, (unsigned)q.nz);
   StageTimer tm(STAGE, st);
@@ -272,9 +303,54 @@ hipError_t launch_stage(const ChainRefs& r, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int NT>
+hipError_t launch_r23_nt(const ChainRefs& r, int nwg, hipStream_t st) {
+  R23Args a;
+  a.N = r.N;
+  a.ns = r.ns;
+  a.Gs = reinterpret_cast<const float*>(r.Gs);
+  a.GbT = reinterpret_cast<const float*>(r.GbT);
+  a.A = reinterpret_cast<const float*>(r.X1);
+  a.C = reinterpret_cast<float*>(r.X2);
+  a.gmax = r.scal + S_GMAX;
+  a.gbmax = r.scal + S_GBMAX;
+  a.amax = r.scal + S_AMAX;
+  a.cmax = r.scal + S_CMAX;
+  StageTimer tm(1, st);
+  hipLaunchKernelGGL((k_r23_h16<NT>), dim3(nwg), dim3(64 * NT), 0, st, a);
+  return hipGetLastError();
+}
+
+// Fused R2+R3 (split float16): A in X1 -> C in X2.
+hipError_t launch_r23(const ChainRefs& r, int nwg, hipStream_t st) {
+  const long long ntask = (long long)r.ns * r.N * r.N;
+  if (nwg > ntask) nwg = (int)ntask;
+  switch ((r.N + 15) / 16) {
+    case 1: return launch_r23_nt<1>(r, nwg, st);
+    case 2: return launch_r23_nt<2>(r, nwg, st);
+    case 3: return launch_r23_nt<3>(r, nwg, st);
+    case 4: return launch_r23_nt<4>(r, nwg, st);
+    case 5: return launch_r23_nt<5>(r, nwg, st);
+    case 6: return launch_r23_nt<6>(r, nwg, st);
+    case 7: return launch_r23_nt<7>(r, nwg, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline bool fused_r23(const ChainRefs& r) {
+  return r.prec == SB2_SPLIT_FP16 && r.N <= R23_MAX_N && r.C3 == nullptr && tune_of(r.N, r.prec).r23 > 0;
+}
+
 template <int PK>
 hipError_t run_chain_pk(const ChainRefs& r, hipStream_t st) {
   hipError_t e;
+  if (PK == PK_H16 && fused_r23(r)) {
+    if ((e = launch_stage<PK, 0>(r, st)) != hipSuccess) return e;
+    if ((e = launch_r23(r, tune_of(r.N, r.prec).r23, st)) != hipSuccess) return e;
+    ChainRefs r4 = r;
+    r4.C3 = r.X2;                                     // the fused kernel leaves C in X2
+    return launch_stage<PK, 3>(r4, st);
+  }
   if ((e = launch_stage<PK, 0>(r, st)) != hipSuccess) return e;
   if ((e = launch_stage<PK, 1>(r, st)) != hipSuccess) return e;
   if ((e = launch_stage<PK, 2>(r, st)) != hipSuccess) return e;
@@ -691,15 +767,28 @@ hipError_t collision_backward(int N, int T, const double* v, const void* h, cons
 // per-system set-up (interaction layout, propagators, GKBA functions) and the
 // collision sums are per-system launches around the rounds.
 // ---------------------------------------------------------------------------
-constexpr size_t BATCH_BUDGET = 48ull << 30;
+constexpr size_t BATCH_BUDGET = 96ull << 30;
 
 struct BatchPlan {
   int rounds = 1;
   std::vector<CollPlan> cp;
   std::vector<size_t> base;
+  std::vector<double> work;   // algorithmic work of one round of each member (S_b N_b^5)
   size_t refs = 0;     // device ChainRefs table
   size_t end = 0;
 };
+
+// Past times of member b per round when the longest member takes R rounds:
+// ceil(T_b / R), but at least enough for 2 S_b N_b >= 768 rows of the first
+// contraction, so that small systems keep full tiles (they then finish in
+// fewer rounds), and at most what one launch's grid.y holds.
+size_t batch_chunk(const sb2_system& q, int R) {
+  size_t S = ((size_t)q.T + R - 1) / R;
+  const size_t smin = (384 + (size_t)q.N - 1) / q.N;
+  if (S < smin) S = smin;
+  if (S > (size_t)q.T) S = q.T;
+  return S;
+}
 
 BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
   BatchPlan bp;
@@ -710,19 +799,25 @@ BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
     bool fits_grid = true;
     for (int b = 0; b < nsys; ++b) {
       const size_t n4 = (size_t)sys[b].N * sys[b].N * sys[b].N * sys[b].N;
-      const size_t S = ((size_t)sys[b].T + R - 1) / R;
+      const size_t S = batch_chunk(sys[b], R);
       tot += S * 2 * 2 * n4 * 2 * bb;
       if (S > 65535 / (2 * (size_t)sys[b].N)) fits_grid = false;
     }
     if ((tot <= BATCH_BUDGET && fits_grid) || R >= SB2_MAX_T) break;
   }
   bp.rounds = R;
+  double wsum = 0.0;
+  for (int b = 0; b < nsys; ++b) {
+    const double n = sys[b].N;
+    bp.work.push_back((double)batch_chunk(sys[b], R) * n * n * n * n * n);
+    wsum += bp.work.back();
+  }
   size_t o = 0;
   bp.refs = o;
   o += al(sizeof(ChainRefs) * MAX_GROUP);
   for (int b = 0; b < nsys; ++b) {
-    const int S = (sys[b].T + R - 1) / R;
-    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S));
+    const int S = (int)batch_chunk(sys[b], R);
+    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S, bp.work[b] / wsum));
     bp.base.push_back(o);
     o += bp.cp.back().end;
   }
@@ -730,17 +825,21 @@ BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
   return bp;
 }
 
+// share[i]: member i's part of the launch's work; the workgroup target of the
+// single-slab stages is divided among the members in that proportion.
 template <int PK, int STAGE>
-hipError_t launch_group(const std::vector<ChainRefs>& refs, const ChainRefs* d_refs, hipStream_t st) {
+hipError_t launch_group(const std::vector<ChainRefs>& refs, const std::vector<double>& share, const ChainRefs* d_refs,
+                        hipStream_t st) {
   GroupTable t;
   t.count = (int)refs.size();
-  t.persist_target = g_persist_target;
   long long off = 0;
   for (int i = 0; i < t.count; ++i) {
     t.off[i] = off;
+    const double want = tune_of(refs[i].N, refs[i].prec).persist * share[i];
+    t.persist[i] = want < 1.0 ? 1 : (int)want;
     int nbatch;
     StreamArgs g = stage_args(STAGE, refs[i], nbatch);
-    off += stage_geom<PK, STAGE>(g, nbatch, t.persist_target).blocks();
+    off += stage_geom<PK, STAGE>(g, nbatch, t.persist[i]).blocks();
   }
   t.off[t.count] = off;
   if (off <= 0) return hipSuccess;
@@ -751,12 +850,13 @@ hipError_t launch_group(const std::vector<ChainRefs>& refs, const ChainRefs* d_r
 }
 
 template <int PK>
-hipError_t group_chain(const std::vector<ChainRefs>& refs, const ChainRefs* d, hipStream_t st) {
+hipError_t group_chain(const std::vector<ChainRefs>& refs, const std::vector<double>& sh, const ChainRefs* d,
+                       hipStream_t st) {
   hipError_t e;
-  if ((e = launch_group<PK, 0>(refs, d, st)) != hipSuccess) return e;
-  if ((e = launch_group<PK, 1>(refs, d, st)) != hipSuccess) return e;
-  if ((e = launch_group<PK, 2>(refs, d, st)) != hipSuccess) return e;
-  return launch_group<PK, 3>(refs, d, st);
+  if ((e = launch_group<PK, 0>(refs, sh, d, st)) != hipSuccess) return e;
+  if ((e = launch_group<PK, 1>(refs, sh, d, st)) != hipSuccess) return e;
+  if ((e = launch_group<PK, 2>(refs, sh, d, st)) != hipSuccess) return e;
+  return launch_group<PK, 3>(refs, sh, d, st);
 }
 
 hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const BatchPlan& bp, void* ws,
@@ -778,6 +878,8 @@ hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const Ba
   for (int r = 0; r < bp.rounds; ++r) {
     std::vector<ChainRefs> refs;
     std::vector<int> who, kk0, nps;
+    std::vector<double> share;
+    double wsum = 0.0;
     for (int b = 0; b < nsys; ++b) {
       const CollPlan& c = bp.cp[b];
       const int k0 = r * c.ch.S;
@@ -793,8 +895,11 @@ hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const Ba
       who.push_back(b);
       kk0.push_back(k0);
       nps.push_back(np);
+      share.push_back(bp.work[b] * np / c.ch.S);
+      wsum += share.back();
     }
     if (refs.empty()) break;
+    for (double& x : share) x /= wsum;
     for (size_t i0 = 0; i0 < refs.size(); i0 += REFS_PER_WRITE) {
       RefsChunk ck;
       ck.count = (int)std::min(refs.size() - i0, (size_t)REFS_PER_WRITE);
@@ -802,9 +907,9 @@ hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const Ba
       hipLaunchKernelGGL(k_write_refs, dim3(1), dim3(64), 0, s, d_refs + i0, ck);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (prec == SB2_FP64) e = group_chain<PK_F64>(refs, d_refs, s);
-    else if (prec == SB2_FP32) e = group_chain<PK_F32>(refs, d_refs, s);
-    else e = group_chain<PK_H16>(refs, d_refs, s);
+    if (prec == SB2_FP64) e = group_chain<PK_F64>(refs, share, d_refs, s);
+    else if (prec == SB2_FP32) e = group_chain<PK_F32>(refs, share, d_refs, s);
+    else e = group_chain<PK_H16>(refs, share, d_refs, s);
     if (e != hipSuccess) return e;
     for (size_t i = 0; i < refs.size(); ++i) {
       const int b = who[i];
@@ -900,6 +1005,9 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
     case SB2_OP_COLLISION_BACKWARD:
       if (T < 1 || T > SB2_MAX_T || prec != SB2_FP64) return 0;
       return bwd_plan(N, T).end;
+    case SB2_OP_AUTOTUNE:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return tune_bytes(N, T, prec);
     default:
       return 0;
   }
@@ -1024,6 +1132,88 @@ int sb2_collision_backward(int N, int T, const double* v, const void* h, const v
   hipError_t e = collision_backward(N, T, v, h, rho_hist, dt, gI, gv, gh, grho, b, ws,
                                     reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? SB2_OK : SB2_EHIP;
+}
+
+int sb2_autotune(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, int prec, void* ws,
+                 size_t ws_bytes, void* stream, int* persist_out, int* r4pct_out, int* fused_out) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  const int Tt = tune_len(N, T, prec);
+  const size_t need = tune_bytes(N, T, prec);
+  if (ws_bytes < need) return SB2_EWORKSPACE;
+  void* Iout = at(ws, need - al((size_t)N * N * C128));     // tail of the workspace: scratch output
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return SB2_EHIP;
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return SB2_EHIP;
+  }
+  const TuneCfg saved = tune_of(N, prec);
+  // time one evaluation of the tuning workload with configuration tc
+  auto trial = [&](const TuneCfg& tc, float& ms) -> int {
+    g_tune[{N, prec}] = tc;
+    if (hipEventRecord(a, s) != hipSuccess) return SB2_EHIP;
+    const int st = sb2_collision(N, Tt, v, h, rho_hist, dt, Iout, nullptr, prec, ws, ws_bytes, stream);
+    if (st != SB2_OK) return st;
+    if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return SB2_EHIP;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? SB2_OK : SB2_EHIP;
+  };
+  TuneCfg best;
+  float best_ms = 0.f, ms = 0.f;
+  int st = trial(best, ms);                       // warm-up
+  if (st == SB2_OK) st = trial(best, best_ms);
+  // coordinate search: workgroup target first, then the split-K factor
+  const int cand_p[] = {256, 512, 1024, 1536, 2048, 3072};
+  const int cand_r[] = {50, 150, 200};
+  for (int pt : cand_p) {
+    if (st != SB2_OK || pt == best.persist) continue;
+    TuneCfg tc = best;
+    tc.persist = pt;
+    st = trial(tc, ms);
+    if (st == SB2_OK && ms < best_ms) { best_ms = ms; best = tc; }
+  }
+  const TuneCfg base = best;
+  for (int rp : cand_r) {
+    if (st != SB2_OK) continue;
+    TuneCfg tc = base;
+    tc.r4pct = rp;
+    st = trial(tc, ms);
+    if (st == SB2_OK && ms < best_ms) { best_ms = ms; best = tc; }
+  }
+  if (prec == SB2_SPLIT_FP16 && N <= R23_MAX_N) {
+    const int cand_f[] = {256, 1024, 2048};
+    const TuneCfg base2 = best;
+    for (int f : cand_f) {
+      if (st != SB2_OK) continue;
+      TuneCfg tc = base2;
+      tc.r23 = f;
+      st = trial(tc, ms);
+      if (st == SB2_OK && ms < best_ms) { best_ms = ms; best = tc; }
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  if (st != SB2_OK) {
+    g_tune[{N, prec}] = saved;
+    return st;
+  }
+  g_tune[{N, prec}] = best;
+  if (persist_out) *persist_out = best.persist;
+  if (r4pct_out) *r4pct_out = best.r4pct;
+  if (fused_out) *fused_out = best.r23;
+  return SB2_OK;
+}
+
+int sb2_set_tuning(int N, int prec, int persist, int r4pct, int fused_wgs) {
+  if (N < 1 || N > SB2_MAX_N || !prec_ok(prec)) return SB2_EINVAL;
+  if (persist < 1 || r4pct < 10 || r4pct > 200 || fused_wgs < 0) return SB2_EINVAL;
+  TuneCfg tc;
+  tc.persist = persist;
+  tc.r4pct = r4pct;
+  tc.r23 = fused_wgs;
+  g_tune[{N, prec}] = tc;
+  return SB2_OK;
 }
 
 size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec) {

@@ -89,3 +89,31 @@ def test_python_binding_rejects_cpu_tensors():
     with pytest.raises(TypeError):
         _lib.sb2_sigma(v, g, g)
     assert ctypes.sizeof(_lib.SystemDesc) >= 48
+
+
+def test_autotune_arguments_and_tuning_table(L):
+    big = 1 << 40
+    a = L.sb2_autotune
+    assert a(0, 10, FAKE, FAKE, FAKE, 0.05, 0, FAKE, big, None, None, None, None) == -2
+    assert a(10, 0, FAKE, FAKE, FAKE, 0.05, 0, FAKE, big, None, None, None, None) == -2
+    assert a(10, 10, None, FAKE, FAKE, 0.05, 0, FAKE, big, None, None, None, None) == -1
+    assert a(10, 10, FAKE, FAKE, FAKE, 0.0, 0, FAKE, big, None, None, None, None) == -1
+    assert a(10, 10, FAKE, FAKE, FAKE, 0.05, 5, FAKE, big, None, None, None, None) == -1
+    assert a(10, 10, FAKE, FAKE, FAKE, 0.05, 0, FAKE, 64, None, None, None, None) == -3
+    ws = _lib.sb2_workspace_size
+    assert ws("autotune", 10, 20, "fp16x3") > ws("collision", 10, 1, "fp16x3")
+    s = L.sb2_set_tuning
+    assert s(0, 0, 768, 100, 512) == -1
+    assert s(10, 9, 768, 100, 512) == -1
+    assert s(10, 0, 0, 100, 512) == -1
+    assert s(10, 0, 768, 5, 512) == -1
+    assert s(10, 0, 768, 201, 512) == -1
+    assert s(10, 0, 768, 100, -1) == -1
+    # workspace sizes do not depend on the tuned values
+    before = [ws(op, 23, 7, p) for op in ("sigma", "collision") for p in ("fp64", "fp32", "fp16x3")]
+    for p in (0, 1, 2):
+        assert s(23, p, 1, 200, 0) == 0
+    after = [ws(op, 23, 7, p) for op in ("sigma", "collision") for p in ("fp64", "fp32", "fp16x3")]
+    for p in (0, 1, 2):
+        assert s(23, p, 768, 100, 512) == 0      # back to the defaults
+    assert before == after
