@@ -28,6 +28,8 @@ struct ChainRefs {
   void* C3;                  // optional separate C buffer (adjoint keeps A, B and C)
   void* part;                // R4 split-K partials
   unsigned* scal;            // split-float16 scale words
+  int chunked;               // n-chunked Vp / C layout (fused split-float16 path)
+  i64 KB;                    // n-block pitch of the chunked Vp rows
 };
 
 __host__ __device__ inline StreamArgs sargs_zero() {

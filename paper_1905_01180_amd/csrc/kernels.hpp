@@ -306,7 +306,8 @@ __global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cpl
 // ---------------------------------------------------------------------------
 // Interaction layouts for the contraction chain:
 //   W_T[x][m], x = (j N + s) N + q:  w_mqsj = 2 v_mqsj - v_qmsj   (row pitch KpW)
-//   V'[i][k],  k = (n N + p) N + r:  v_irpn                        (row pitch KpV)
+//   V'[i][n nstride + p N + r] = v_irpn  (row pitch KpV; nstride = N^2, or N^2
+//                                         rounded up to 8 for the n-chunked layout)
 // Stored in the bulk type, or (split float16) as hi / lo planes of
 // x 2^e with 2^e from the recorded max (two passes: k_max_vw, then the writers).
 // ---------------------------------------------------------------------------
@@ -384,8 +385,8 @@ __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* _
 
 // one workgroup per (i, p): 32 x 32 LDS transposes of the (r, n) block
 template <typename T>
-__global__ void __launch_bounds__(256) k_prep_vpt(int N, i64 KpV, const double* __restrict__ v, T* __restrict__ Vp,
-                                                   i64 plane, const unsigned* vmax) {
+__global__ void __launch_bounds__(256) k_prep_vpt(int N, i64 KpV, i64 nstride, const double* __restrict__ v,
+                                                   T* __restrict__ Vp, i64 plane, const unsigned* vmax) {
   __shared__ double tile[32][33];
   const int i = blockIdx.x / N, p = blockIdx.x % N;
   const i64 nn = (i64)N * N;
@@ -401,7 +402,7 @@ __global__ void __launch_bounds__(256) k_prep_vpt(int N, i64 KpV, const double* 
       __syncthreads();
       for (int yy = ty; yy < 32; yy += 8) {
         const int n = n0 + yy, r = r0 + tx;
-        if (r < N && n < N) put_val<T>(Vp, plane, (i64)i * KpV + ((i64)n * N + p) * N + r, tile[tx][yy], sc);
+        if (r < N && n < N) put_val<T>(Vp, plane, (i64)i * KpV + (i64)n * nstride + (i64)p * N + r, tile[tx][yy], sc);
       }
     }
 }

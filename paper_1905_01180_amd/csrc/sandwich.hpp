@@ -48,7 +48,8 @@ struct R23Args {
   const float* Gs;           // [b][p][q] complex float32
   const float* GbT;          // [b][r][s] complex float32
   const float* A;            // [b][n][j][s][q] complex float32
-  float* C;                  // [b][j][n][p][r] complex float32 (out)
+  float* C;                  // complex float32 (out): [b][j][n][p][r], or [n][b][j][p][r] when chunked
+  int chunked;
   const unsigned* gmax;      // recorded max |x| of Gs, GbT, A (float bits)
   const unsigned* gbmax;
   const unsigned* amax;
@@ -260,7 +261,8 @@ __global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
     }
 
     // ---- store C_bjn[p][r], r = 16 rt + 4 g + i: 32 contiguous bytes per lane ----
-    float2* dst = reinterpret_cast<float2*>(a.C) + ((b * N + j) * N + n) * nn + (i64)p * N;
+    const i64 blk = a.chunked ? ((i64)n * a.ns + b) * N + j : (b * N + j) * N + n;
+    float2* dst = reinterpret_cast<float2*>(a.C) + blk * nn + (i64)p * N;
     const bool vec = (N & 1) == 0;                    // 16-byte aligned rows
 #pragma unroll
     for (int rt = 0; rt < NT; ++rt) {

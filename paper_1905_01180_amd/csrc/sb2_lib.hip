@@ -25,6 +25,7 @@
 #include "kernels.hpp"
 #include "chain.hpp"
 #include "sandwich.hpp"
+#include "r4.hpp"
 #include "sb2.h"
 
 using namespace sb2;
@@ -103,6 +104,12 @@ TuneCfg tune_of(int N, int prec) {
 struct ChainPlan {
   int N = 0, S = 0, nz = 1, kchunk = 1;
   i64 KpW = 0, KpV = 0;                 // row pitches of W_T and Vp
+  // n-chunked layout (split float16 with the fused second/third contraction):
+  // Vp[i][n KB + (p N + r)] with KB = N^2 rounded up to 8 (zero padding), C
+  // stored as [n][(b, j)][(p, r)], and the last contraction split into the N
+  // chunks n
+  bool chunked = false;
+  i64 KB = 0;
   size_t w = 0, vp = 0, gs = 0, gbs = 0, x1 = 0, x2 = 0, part = 0, scal = 0, end = 0;
 };
 
@@ -130,7 +137,8 @@ void r4_split(int N, int ns, int prec, int& nz, int& kchunk, double scale = 1.0)
 
 // share: this chain's part of a grouped launch (1 when it runs alone); scales
 // the R4 split so that the whole launch, not each member, fills the chip.
-ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0, double share = 1.0) {
+ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0, double share = 1.0,
+                     bool allow_chunked = true) {
   ChainPlan p;
   p.N = N;
   const size_t n4 = (size_t)N * N * N * N, n3 = (size_t)N * N * N, n2 = (size_t)N * N;
@@ -144,19 +152,31 @@ ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0, do
   p.S = (int)S;
   p.KpW = (N + 7) / 8 * 8;
   p.KpV = ((i64)n3 + 7) / 8 * 8;
+  p.KB = ((i64)n2 + 7) / 8 * 8;
   int nz_max, kc_max;
   r4_split(N, 2 * p.S, prec, nz_max, kc_max, 2.0);
   r4_split(N, 2 * p.S, prec, p.nz, p.kchunk, tune_of(N, prec).r4pct / 100.0 * share);
   if (p.nz > nz_max) nz_max = p.nz;
+  // buffer sizes cover both layouts, so they do not depend on tuned values
+  const bool h16 = prec == SB2_SPLIT_FP16;
+  if (h16 && nz_max < N) nz_max = N;
+  const i64 vrow = h16 ? std::max(p.KpV, (i64)N * p.KB) : p.KpV;
+  p.chunked = allow_chunked && h16 && N <= R23_MAX_N && tune_of(N, prec).r23 > 0;
+  if (p.chunked) {
+    p.KpV = (i64)N * p.KB;
+    p.nz = N;
+    p.kchunk = (int)n2;
+  }
   const size_t ib = inter_bytes(prec);
   size_t o = base;
   p.scal = o; o += al(S_NWORDS * 4);
   p.w = o; o += al(n3 * (size_t)p.KpW * ib);
-  p.vp = o; o += al((size_t)N * (size_t)p.KpV * ib);
+  p.vp = o; o += al((size_t)N * (size_t)vrow * ib);
   p.gs = o; o += al(2 * S * n2 * 2 * bb);
   p.gbs = o; o += al(2 * S * n2 * 2 * bb);
-  p.x1 = o; o += al(2 * S * n4 * 2 * bb);
-  p.x2 = o; o += al(2 * S * n4 * 2 * bb);
+  // (+64 bytes: the last contraction may read up to 7 elements past a row end)
+  p.x1 = o; o += al(2 * S * n4 * 2 * bb + 64);
+  p.x2 = o; o += al(2 * S * n4 * 2 * bb + 64);
   p.part = o; o += al((size_t)nz_max * N * 2 * S * N * C128);
   p.end = o;
   return p;
@@ -168,7 +188,7 @@ struct CollPlan {
   size_t end;
 };
 
-CollPlan coll_plan(int N, int T, int prec, int forceS = 0, double share = 1.0) {
+CollPlan coll_plan(int N, int T, int prec, int forceS = 0, double share = 1.0, bool allow_chunked = true) {
   CollPlan c;
   const size_t hist = (size_t)T * N * N * C128;
   size_t o = 0;
@@ -184,7 +204,7 @@ CollPlan coll_plan(int N, int T, int prec, int forceS = 0, double share = 1.0) {
   c.terms = o; o += al(hist);
   c.ex1 = o; o += al((size_t)N * N * C128);
   c.ex2 = o; o += al((size_t)N * N * C128);
-  c.ch = chain_plan(N, T, prec, o, forceS, share);
+  c.ch = chain_plan(N, T, prec, o, forceS, share, allow_chunked);
   c.end = c.ch.end;
   return c;
 }
@@ -266,8 +286,13 @@ hipError_t prep_interaction(int N, const double* v, const ChainPlan& p, void* ws
   const i64 planeW = (i64)N * N * N * p.KpW, planeV = (i64)N * p.KpV;
   hipLaunchKernelGGL(k_prep_wt<T>, dim3(N * nj * nm), dim3(256), 0, s, N, (int)p.KpW, v,
                      reinterpret_cast<T*>(at(ws, p.w)), planeW, h ? scal + S_WMAX : nullptr);
-  hipLaunchKernelGGL(k_prep_vpt<T>, dim3(N * N), dim3(256), 0, s, N, p.KpV, v, reinterpret_cast<T*>(at(ws, p.vp)),
-                     planeV, h ? scal + S_VMAX : nullptr);
+  if (p.chunked) {                               // zero n-block padding
+    const long long words = (long long)N * p.KpV;  // two float16 planes: N KpV 32-bit words
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks(words, 256)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned*>(at(ws, p.vp)), (int)words, 0u);
+  }
+  hipLaunchKernelGGL(k_prep_vpt<T>, dim3(N * N), dim3(256), 0, s, N, p.KpV, p.chunked ? p.KB : (i64)N * N, v,
+                     reinterpret_cast<T*>(at(ws, p.vp)), planeV, h ? scal + S_VMAX : nullptr);
   return hipGetLastError();
 }
 
@@ -288,6 +313,8 @@ ChainRefs chain_refs(int prec, int N, int ns, const ChainPlan& p, void* ws, void
   r.C3 = cbuf;
   r.part = at(ws, p.part);
   r.scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
+  r.chunked = p.chunked ? 1 : 0;
+  r.KB = p.KB;
   return r;
 }
 
@@ -316,6 +343,7 @@ hipError_t launch_r23_nt(const ChainRefs& r, int nwg, hipStream_t st) {
   a.gbmax = r.scal + S_GBMAX;
   a.amax = r.scal + S_AMAX;
   a.cmax = r.scal + S_CMAX;
+  a.chunked = r.chunked;
   StageTimer tm(1, st);
   hipLaunchKernelGGL((k_r23_h16<NT>), dim3(nwg), dim3(64 * NT), 0, st, a);
   return hipGetLastError();
@@ -337,9 +365,42 @@ hipError_t launch_r23(const ChainRefs& r, int nwg, hipStream_t st) {
   }
 }
 
-inline bool fused_r23(const ChainRefs& r) {
-  return r.prec == SB2_SPLIT_FP16 && r.N <= R23_MAX_N && r.C3 == nullptr && tune_of(r.N, r.prec).r23 > 0;
+template <int FS>
+hipError_t launch_r4_fs(const ChainRefs& r, hipStream_t st) {
+  R4Args a;
+  a.M = r.N;
+  a.ncol = r.ns * r.N;
+  a.kc = r.N * r.N;
+  a.V = reinterpret_cast<const _Float16*>(r.Vp);
+  a.ldv = r.KpV;
+  a.vplane = (i64)r.N * r.KpV;
+  a.vchunk = r.KB;
+  a.X = reinterpret_cast<const float*>(r.C3 ? r.C3 : r.X1);
+  a.xchunk = (i64)a.ncol * a.kc;
+  a.part = reinterpret_cast<double*>(r.part);
+  a.vmax = r.scal + S_VMAX;
+  a.xmax = r.scal + S_CMAX;
+  StageTimer tm(3, st);
+  hipLaunchKernelGGL((k_r4_h16<FS>), dim3((unsigned)((a.ncol + 63) / 64), (unsigned)r.N), dim3(512), 0, st, a);
+  return hipGetLastError();
 }
+
+// Last contraction, split float16, n-chunked layout (one chunk per n).
+hipError_t launch_r4_h16(const ChainRefs& r, hipStream_t st) {
+  switch ((r.N + 15) / 16) {
+    case 1: return launch_r4_fs<1>(r, st);
+    case 2: return launch_r4_fs<2>(r, st);
+    case 3: return launch_r4_fs<3>(r, st);
+    case 4: return launch_r4_fs<4>(r, st);
+    case 5: return launch_r4_fs<5>(r, st);
+    case 6: return launch_r4_fs<6>(r, st);
+    case 7: return launch_r4_fs<7>(r, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// the plan decides: the n-chunked layout goes with the fused kernel
+inline bool fused_r23(const ChainRefs& r) { return r.prec == SB2_SPLIT_FP16 && r.chunked && r.C3 == nullptr; }
 
 template <int PK>
 hipError_t run_chain_pk(const ChainRefs& r, hipStream_t st) {
@@ -349,7 +410,7 @@ hipError_t run_chain_pk(const ChainRefs& r, hipStream_t st) {
     if ((e = launch_r23(r, tune_of(r.N, r.prec).r23, st)) != hipSuccess) return e;
     ChainRefs r4 = r;
     r4.C3 = r.X2;                                     // the fused kernel leaves C in X2
-    return launch_stage<PK, 3>(r4, st);
+    return launch_r4_h16(r4, st);
   }
   if ((e = launch_stage<PK, 0>(r, st)) != hipSuccess) return e;
   if ((e = launch_stage<PK, 1>(r, st)) != hipSuccess) return e;
@@ -817,7 +878,7 @@ BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
   o += al(sizeof(ChainRefs) * MAX_GROUP);
   for (int b = 0; b < nsys; ++b) {
     const int S = (int)batch_chunk(sys[b], R);
-    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S, bp.work[b] / wsum));
+    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S, bp.work[b] / wsum, false));
     bp.base.push_back(o);
     o += bp.cp.back().end;
   }
