@@ -34,7 +34,9 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "fp16x3": 2516.0}   # MI355X dense m
 STAGES = ["R1", "R2", "R3", "R4", "layout", "gkba", "pack+reduce", "collision"]
 # algorithmic real flops per slice (one self-energy) and stage: complex x real = 4, complex x complex = 8
 STAGE_FLOPS_PER_N5 = {"R1": 4, "R2": 8, "R3": 8, "R4": 4}
-KERNEL_SOURCES = ["paper_1905_01180_amd/csrc/gemm.hpp", "paper_1905_01180_amd/csrc/stream_gemm.hpp"]
+KERNEL_SOURCES = ["paper_1905_01180_amd/csrc/gemm.hpp", "paper_1905_01180_amd/csrc/stream_gemm.hpp",
+                  "paper_1905_01180_amd/csrc/chain.hpp", "paper_1905_01180_amd/csrc/sandwich.hpp",
+                  "paper_1905_01180_amd/csrc/r4.hpp"]
 
 
 def log(*a):
@@ -174,14 +176,20 @@ def main():
     # dominant contraction kernel
     roof = None
     if stages:
-        dom = max(("R1", "R2", "R3", "R4"), key=lambda k: stages[k]["ms_per_step"])
+        fused = stages["R3"]["launches_per_step"] == 0 and stages["R2"]["launches_per_step"] > 0
+        if fused:                        # the R2 slot times the fused second+third contraction
+            stages["R2+R3"] = stages.pop("R2")
+            stages.pop("R3")
+        flops_n5 = dict(STAGE_FLOPS_PER_N5, **{"R2+R3": 16})
+        dom = max((k for k in ("R1", "R2", "R3", "R2+R3", "R4") if k in stages),
+                  key=lambda k: stages[k]["ms_per_step"])
         st = stages[dom]
         per_launch_ms = st["ms_per_step"] / max(st["launches_per_step"], 1e-9)
-        flops_per_launch = STAGE_FLOPS_PER_N5[dom] * n5 * 2 * args.t / st["launches_per_step"]
+        flops_per_launch = flops_n5[dom] * n5 * 2 * args.t / st["launches_per_step"]
         achieved = flops_per_launch / (per_launch_ms * 1e-3) / 1e12
         peak = PEAK_TFLOPS[args.prec]
         traffic = None
-        tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.prec}_n{args.n}.json")
+        tf = os.path.join(ROOT, "profiles", f"traffic_{dom.replace('+', '')}_{args.prec}_n{args.n}.json")
         if os.path.exists(tf):
             with open(tf) as fh:
                 tj = json.load(fh)

@@ -17,8 +17,8 @@
 //   sum over slots of [a_re, a_im] . [b_im,  b_re] = Im sum a b.
 // One MFMA therefore contracts 16 complex indices for one real output part.
 //
-// Workgroup: NT = ceil(N/16) waves; wave w owns the 16 columns p = 16w..16w+15
-// of Y^T and of C^T for every task.
+// Workgroup: NT = ceil(N/16) waves; wave w owns the 16 indices p = 16w..16w+15
+// of Y and of C for every task.
 //   * G_b[p][:] of the wave's columns: both B operands of step 1, split,
 //     kept in registers for the whole slice.
 //   * Gbt_b: staged in LDS once per slice b, split, in the slot order above.
@@ -31,7 +31,10 @@
 //           accumulators hold rows s = 16c + 4g + i (i = slot 0..3) of column
 //           p = lane%16, i.e. exactly the four s indices that lane group g
 //           supplies as B operand of
-//   step 2  C^T[r][p] += sum_{s in slab} Gbt[r][s] Y^T[s][p].
+//   step 2  C[p][r] += sum_{s in slab} Y[p][s] Gbt[r][s], with those
+//           accumulators as the A operand (a lane supplies row p = lane%16 and
+//           the K slots of its group in both operand roles), so C comes out
+//           with 16 consecutive r across the lanes of a row.
 // Split float16: x 2^e = hi + lo (hi, lo float16, |x 2^e| < 2^14), three MFMAs
 // per real product; A, G and Gbt take 2^e from their recorded maxima, Y from
 // the bound |Y| <= 2 N max|A| max|G|.  The kernel raises the recorded max |C|
@@ -196,6 +199,40 @@ __global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
     cr[i] = vzero<fx4>();
     ci[i] = vzero<fx4>();
   }
+  // B operands of step 2 for the most recent slab: [Y_re, -Y_im] and
+  // [Y_im, Y_re] at s = 16c + 4g + i
+  hx8 pre_h, pre_l, pim_h, pim_l;
+  auto split_y = [&](const fx4& yr, const fx4& yi) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      _Float16 rh, rl, ih, il;
+      split_h(yr[i] * fy, rh, rl);
+      split_h(yi[i] * fy, ih, il);
+      pre_h[i] = rh;
+      pre_l[i] = rl;
+      pre_h[4 + i] = -ih;
+      pre_l[4 + i] = -il;
+      pim_h[i] = ih;
+      pim_l[i] = il;
+      pim_h[4 + i] = rh;
+      pim_l[4 + i] = rl;
+    }
+  };
+  // step 2 for slab cs: C[p][r] += Y[p][slab] Gbt[r][slab] with Y as the A
+  // operand (lane: row p, the slab's s slots) and Gbt as the B operand (lane:
+  // column r), so that the accumulators hold rows p = 16w + 4g + i and 16
+  // consecutive columns r = 16 rt + lane%16
+  auto step2 = [&](int cs) {
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt) {
+      const int row = 16 * rt + lr, col = 32 * cs + 8 * grp;
+      const hx8 gh = *reinterpret_cast<const hx8*>(&sG[0][row][col]);
+      const hx8 gl = *reinterpret_cast<const hx8*>(&sG[1][row][col]);
+      cr[rt] = mma3(pre_h, pre_l, gh, gl, cr[rt]);
+      ci[rt] = mma3(pim_h, pim_l, gh, gl, ci[rt]);
+    }
+  };
+
   float mx = 0.f;
   i64 cur_b = -1;
   int buf = 0;
@@ -231,62 +268,28 @@ __global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
         yr = mma3(ah, al, bre_h[qc], bre_l[qc], yr);
         yi = mma3(ah, al, bim_h[qc], bim_l[qc], yi);
       }
-      // B operands of step 2: [Y_re, -Y_im] and [Y_im, Y_re] at s = 16c + 4g + i
-      hx8 pre_h, pre_l, pim_h, pim_l;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        _Float16 rh, rl, ih, il;
-        split_h(yr[i] * fy, rh, rl);
-        split_h(yi[i] * fy, ih, il);
-        pre_h[i] = rh;
-        pre_l[i] = rl;
-        pre_h[4 + i] = -ih;
-        pre_l[4 + i] = -il;
-        pim_h[i] = ih;
-        pim_l[i] = il;
-        pim_h[4 + i] = rh;
-        pim_l[4 + i] = rl;
-      }
-
-      // step 2: C^T[r][p] += Gbt[r][slab] Y^T[slab][p]
-#pragma unroll
-      for (int rt = 0; rt < NT; ++rt) {
-        const int row = 16 * rt + lr, col = 32 * c + 8 * grp;
-        const hx8 gh = *reinterpret_cast<const hx8*>(&sG[0][row][col]);
-        const hx8 gl = *reinterpret_cast<const hx8*>(&sG[1][row][col]);
-        cr[rt] = mma3(gh, gl, pre_h, pre_l, cr[rt]);
-        ci[rt] = mma3(gh, gl, pim_h, pim_l, ci[rt]);
-      }
+      // step 2 of the previous slab: its products keep the matrix cores busy
+      // while this slab's step-1 results drain and are split
+      if (c > 0) step2(c - 1);
+      split_y(yr, yi);
       buf ^= 1;
     }
+    step2(NT - 1);
 
-    // ---- store C_bjn[p][r], r = 16 rt + 4 g + i: 32 contiguous bytes per lane ----
+    // ---- store C_bjn[p][r], p = 16 w + 4 g + i, r = 16 rt + lane%16: each
+    // store instruction writes 16 consecutive r (128 bytes) of four rows p ----
     const i64 blk = a.chunked ? ((i64)n * a.ns + b) * N + j : (b * N + j) * N + n;
-    float2* dst = reinterpret_cast<float2*>(a.C) + blk * nn + (i64)p * N;
-    const bool vec = (N & 1) == 0;                    // 16-byte aligned rows
+    float2* dst = reinterpret_cast<float2*>(a.C) + blk * nn;
 #pragma unroll
     for (int rt = 0; rt < NT; ++rt) {
-      const int r0 = 16 * rt + 4 * grp;
-      float v[8];
+      const int r = 16 * rt + lr;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        v[2 * i] = cr[rt][i] * unscale;
-        v[2 * i + 1] = ci[rt][i] * unscale;
-      }
-      if (p < N) {
-        if (vec && r0 + 3 < N) {
-          float4* d4 = reinterpret_cast<float4*>(dst + r0);
-          d4[0] = make_float4(v[0], v[1], v[2], v[3]);
-          d4[1] = make_float4(v[4], v[5], v[6], v[7]);
-#pragma unroll
-          for (int i = 0; i < 8; ++i) mx = fmaxf(mx, fabsf(v[i]));
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (r0 + i < N) {
-              dst[r0 + i] = make_float2(v[2 * i], v[2 * i + 1]);
-              mx = fmaxf(mx, fmaxf(fabsf(v[2 * i]), fabsf(v[2 * i + 1])));
-            }
+        const int pp = 16 * w + 4 * grp + i;
+        const float re = cr[rt][i] * unscale, im = ci[rt][i] * unscale;
+        if (pp < N && r < N) {
+          dst[(i64)pp * N + r] = make_float2(re, im);
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
         }
       }
       cr[rt] = vzero<fx4>();
