@@ -134,13 +134,19 @@ typedef struct {
   void* I_out;           /* N x N complex (out)    */
 } sb2_system;
 
-/* sb2_collision_batched -- sb2_collision for nsys independent systems of
- * uneven N and T in one enqueue: every stage runs as one persistent launch
- * over the work items of all systems (the descriptor array `sys` is read on
- * the host; every pointer in it is a device pointer).  Results equal nsys
- * calls of sb2_collision with the same prec up to the order of float32
- * accumulation.  Errors: as sb2_collision for any system; SB2_EINVAL for
- * nsys < 1 or sys == NULL.                                                   */
+/* sb2_collision_batched -- sb2_collision for nsys <= 64 independent systems
+ * of uneven N and T in one enqueue (the descriptor array `sys` is read on the
+ * host; every pointer in it is a device pointer).  Systems with less than
+ * 10^12 flops of contraction work (48 T N^5) are grouped: those with the same
+ * ceil(N/16) form a bucket, the buckets run one after the other, and within a
+ * bucket the past times of all systems are processed in common rounds, every
+ * contraction stage of a round being one launch over the work items of all
+ * the bucket's systems.  Larger systems fill the chip with their own launches
+ * and run as in sb2_collision, after the buckets.  Nothing is allocated or synchronised, so the call
+ * can be captured in a HIP graph.  Results equal nsys calls of sb2_collision
+ * with the same prec up to the order of float32 accumulation.  Errors: as
+ * sb2_collision for any system; SB2_EINVAL for nsys < 1 or sys == NULL;
+ * SB2_ESHAPE for nsys > 64.                                                  */
 int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, size_t ws_bytes,
                           void* stream);
 size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec);

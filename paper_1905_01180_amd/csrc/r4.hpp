@@ -40,8 +40,9 @@ struct R4Args {
   const unsigned* xmax;
 };
 
+// Workgroup (bx, by): columns 64 bx .., chunk by.
 template <int FS>
-__global__ void __launch_bounds__(512) k_r4_h16(const R4Args a) {
+__device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
   constexpr int NTH = 512, NCOL = 64, KS = 64, NKG = KS / 32;
   constexpr int FSP = (FS + 1) / 2 * 2, FH = FSP / 2;   // padded row fragments, per row half
   constexpr int LP = KS + 8;                            // 144-byte rows: 16 mod 128
@@ -54,12 +55,12 @@ __global__ void __launch_bounds__(512) k_r4_h16(const R4Args a) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int grp = lane >> 4, lr = lane & 15;
   const int rh = w >> 2, cg = w & 3;
-  const int col0 = blockIdx.x * NCOL;
+  const int col0 = bx * NCOL;
   // k: index within the chunk, 0 .. kc - 1
   const int k0 = 0, k1 = a.kc, K = a.kc;
   const int nslab = (k1 + KS - 1) / KS;
-  const _Float16* Vz = a.V + (i64)blockIdx.y * a.vchunk;
-  const float* Xz = a.X + 2 * ((i64)blockIdx.y * a.xchunk);
+  const _Float16* Vz = a.V + (i64)by * a.vchunk;
+  const float* Xz = a.X + 2 * ((i64)by * a.xchunk);
   const float sv = split_scale(a.vmax), sx = split_scale(a.xmax);
   const double unscale = 1.0 / ((double)sv * (double)sx);
 
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__(512) k_r4_h16(const R4Args a) {
   // ---- partial sums: part[n][i][c], i = 16 f + 4 g + q ----
   const int c = col0 + 16 * cg + lr;
   if (c < a.ncol) {
-    double2* out = reinterpret_cast<double2*>(a.part) + (i64)blockIdx.y * a.M * a.ncol + c;
+    double2* out = reinterpret_cast<double2*>(a.part) + (i64)by * a.M * a.ncol + c;
 #pragma unroll
     for (int f = 0; f < FH; ++f) {
 #pragma unroll
@@ -234,6 +235,11 @@ __global__ void __launch_bounds__(512) k_r4_h16(const R4Args a) {
       }
     }
   }
+}
+
+template <int FS>
+__global__ void __launch_bounds__(512) k_r4_h16(const R4Args a) {
+  r4_body<FS>(a, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace sb2

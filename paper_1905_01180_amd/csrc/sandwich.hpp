@@ -84,8 +84,9 @@ struct R23Cfg {
   static constexpr int LP = KW + (((16 - (KW * 2) % 128) + 128) % 128) / 2;
 };
 
+// Workgroup wg of nwg: tasks [ntask wg / nwg, ntask (wg + 1) / nwg).
 template <int NT>
-__global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
+__device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
   using C_ = R23Cfg<NT>;
   constexpr int KW = C_::KW, LP = C_::LP, NTH = C_::NTH;
   __shared__ __attribute__((aligned(16))) _Float16 sG[2][16 * NT][LP];   // Gbt slots: hi, lo
@@ -97,7 +98,7 @@ __global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
   const int grp = lane >> 4, lr = lane & 15;
   const i64 nn = (i64)N * N;
   const i64 ntask = (i64)a.ns * nn;
-  const i64 t0 = ntask * blockIdx.x / gridDim.x, t1 = ntask * (blockIdx.x + 1) / gridDim.x;
+  const i64 t0 = ntask * wg / nwg, t1 = ntask * (wg + 1) / nwg;
   // scales as exponents, so that no product of scales can overflow
   int ea, eg, egb;
   bool okA, okG, okGb;
@@ -306,6 +307,11 @@ __global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
     for (int i = 0; i < NT; ++i) m = fmaxf(m, red[i]);
     if (m > 0.f) atomicMax(a.cmax, __float_as_uint(m));
   }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
+  r23_body<NT>(a, blockIdx.x, gridDim.x);
 }
 
 }  // namespace sb2

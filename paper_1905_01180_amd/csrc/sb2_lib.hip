@@ -24,8 +24,7 @@
 
 #include "kernels.hpp"
 #include "chain.hpp"
-#include "sandwich.hpp"
-#include "r4.hpp"
+#include "group.hpp"
 #include "sb2.h"
 
 using namespace sb2;
@@ -332,25 +331,17 @@ hipError_t launch_stage(const ChainRefs& r, hipStream_t st) {
 
 template <int NT>
 hipError_t launch_r23_nt(const ChainRefs& r, int nwg, hipStream_t st) {
-  R23Args a;
-  a.N = r.N;
-  a.ns = r.ns;
-  a.Gs = reinterpret_cast<const float*>(r.Gs);
-  a.GbT = reinterpret_cast<const float*>(r.GbT);
-  a.A = reinterpret_cast<const float*>(r.X1);
-  a.C = reinterpret_cast<float*>(r.X2);
-  a.gmax = r.scal + S_GMAX;
-  a.gbmax = r.scal + S_GBMAX;
-  a.amax = r.scal + S_AMAX;
-  a.cmax = r.scal + S_CMAX;
-  a.chunked = r.chunked;
+  const R23Args a = r23_args(r);
   StageTimer tm(1, st);
   hipLaunchKernelGGL((k_r23_h16<NT>), dim3(nwg), dim3(64 * NT), 0, st, a);
   return hipGetLastError();
 }
 
+// Workgroups of a fused launch (tuned per N and precision).
+inline long long r23_wgs(int N, int prec) { return tune_of(N, prec).r23; }
+
 // Fused R2+R3 (split float16): A in X1 -> C in X2.
-hipError_t launch_r23(const ChainRefs& r, int nwg, hipStream_t st) {
+hipError_t launch_r23(const ChainRefs& r, long long nwg, hipStream_t st) {
   const long long ntask = (long long)r.ns * r.N * r.N;
   if (nwg > ntask) nwg = (int)ntask;
   switch ((r.N + 15) / 16) {
@@ -367,21 +358,9 @@ hipError_t launch_r23(const ChainRefs& r, int nwg, hipStream_t st) {
 
 template <int FS>
 hipError_t launch_r4_fs(const ChainRefs& r, hipStream_t st) {
-  R4Args a;
-  a.M = r.N;
-  a.ncol = r.ns * r.N;
-  a.kc = r.N * r.N;
-  a.V = reinterpret_cast<const _Float16*>(r.Vp);
-  a.ldv = r.KpV;
-  a.vplane = (i64)r.N * r.KpV;
-  a.vchunk = r.KB;
-  a.X = reinterpret_cast<const float*>(r.C3 ? r.C3 : r.X1);
-  a.xchunk = (i64)a.ncol * a.kc;
-  a.part = reinterpret_cast<double*>(r.part);
-  a.vmax = r.scal + S_VMAX;
-  a.xmax = r.scal + S_CMAX;
+  const R4Args a = r4_args(r);
   StageTimer tm(3, st);
-  hipLaunchKernelGGL((k_r4_h16<FS>), dim3((unsigned)((a.ncol + 63) / 64), (unsigned)r.N), dim3(512), 0, st, a);
+  hipLaunchKernelGGL((k_r4_h16<FS>), dim3((unsigned)r4_tiles(a), (unsigned)r.N), dim3(512), 0, st, a);
   return hipGetLastError();
 }
 
@@ -407,10 +386,8 @@ hipError_t run_chain_pk(const ChainRefs& r, hipStream_t st) {
   hipError_t e;
   if (PK == PK_H16 && fused_r23(r)) {
     if ((e = launch_stage<PK, 0>(r, st)) != hipSuccess) return e;
-    if ((e = launch_r23(r, tune_of(r.N, r.prec).r23, st)) != hipSuccess) return e;
-    ChainRefs r4 = r;
-    r4.C3 = r.X2;                                     // the fused kernel leaves C in X2
-    return launch_r4_h16(r4, st);
+    if ((e = launch_r23(r, r23_wgs(r.N, r.prec), st)) != hipSuccess) return e;
+    return launch_r4_h16(r, st);                      // the fused kernel leaves C in X2
   }
   if ((e = launch_stage<PK, 0>(r, st)) != hipSuccess) return e;
   if ((e = launch_stage<PK, 1>(r, st)) != hipSuccess) return e;
@@ -832,6 +809,7 @@ constexpr size_t BATCH_BUDGET = 96ull << 30;
 
 struct BatchPlan {
   int rounds = 1;
+  bool chunked = false;     // members use the fused split-float16 chain
   std::vector<CollPlan> cp;
   std::vector<size_t> base;
   std::vector<double> work;   // algorithmic work of one round of each member (S_b N_b^5)
@@ -853,6 +831,11 @@ size_t batch_chunk(const sb2_system& q, int R) {
 
 BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
   BatchPlan bp;
+  // the fused split-float16 path (n-chunked layouts) when every member can take it
+  bool chunked = prec == SB2_SPLIT_FP16;
+  for (int b = 0; b < nsys; ++b)
+    if (sys[b].N > R23_MAX_N || tune_of(sys[b].N, prec).r23 <= 0) chunked = false;
+  bp.chunked = chunked;
   const size_t bb = bulk_bytes(prec);
   int R = 1;
   for (;; ++R) {
@@ -878,7 +861,7 @@ BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
   o += al(sizeof(ChainRefs) * MAX_GROUP);
   for (int b = 0; b < nsys; ++b) {
     const int S = (int)batch_chunk(sys[b], R);
-    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S, bp.work[b] / wsum, false));
+    bp.cp.push_back(coll_plan(sys[b].N, sys[b].T, prec, S, bp.work[b] / wsum, chunked));
     bp.base.push_back(o);
     o += bp.cp.back().end;
   }
@@ -918,6 +901,91 @@ hipError_t group_chain(const std::vector<ChainRefs>& refs, const std::vector<dou
   if ((e = launch_group<PK, 1>(refs, sh, d, st)) != hipSuccess) return e;
   if ((e = launch_group<PK, 2>(refs, sh, d, st)) != hipSuccess) return e;
   return launch_group<PK, 3>(refs, sh, d, st);
+}
+
+template <int NT>
+hipError_t launch_bucket(const ChainRefs* d, const SubGroup& t23, const SubGroup& t4, hipStream_t st) {
+  hipError_t e;
+  {
+    StageTimer tm(1, st);
+    hipLaunchKernelGGL((k_r23_group<NT>), dim3((unsigned)t23.off[t23.count]), dim3(64 * NT), 0, st, d, t23);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  StageTimer tm(3, st);
+  hipLaunchKernelGGL((k_r4_group<NT>), dim3((unsigned)t4.off[t4.count]), dim3(512), 0, st, d, t4);
+  return hipGetLastError();
+}
+
+// One round of the n-chunked split-float16 chain over all members: the first
+// contraction as one grouped launch, then per 16-wide bucket of N one launch
+// of the fused second+third and one of the last contraction.  Each bucket's
+// fused launch gets about the single-system workgroup count, divided among
+// its members by work.
+hipError_t group_chain_h16(const std::vector<ChainRefs>& refs, const std::vector<double>& share, const ChainRefs* d,
+                           hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_group<PK_H16, 0>(refs, share, d, st)) != hipSuccess) return e;
+  for (int nt = 1; nt <= 7; ++nt) {
+    SubGroup t23, t4;
+    t23.count = t4.count = 0;
+    double wsum = 0.0;
+    for (size_t i = 0; i < refs.size(); ++i)
+      if ((refs[i].N + 15) / 16 == nt) wsum += share[i];
+    long long o23 = 0, o4 = 0;
+    for (size_t i = 0; i < refs.size(); ++i) {
+      if ((refs[i].N + 15) / 16 != nt) continue;
+      const long long ntask = (long long)refs[i].ns * refs[i].N * refs[i].N;
+      long long nwg = (long long)(r23_wgs(refs[i].N, refs[i].prec) * share[i] / wsum + 0.5);
+      if (nwg < 1) nwg = 1;
+      if (nwg > ntask) nwg = ntask;
+      t23.idx[t23.count] = t4.idx[t4.count] = (int)i;
+      t23.off[t23.count++] = o23;
+      t4.off[t4.count++] = o4;
+      o23 += nwg;
+      o4 += (long long)r4_tiles(r4_args(refs[i])) * refs[i].N;
+    }
+    if (t23.count == 0) continue;
+    t23.off[t23.count] = o23;
+    t4.off[t4.count] = o4;
+    switch (nt) {
+      case 1: e = launch_bucket<1>(d, t23, t4, st); break;
+      case 2: e = launch_bucket<2>(d, t23, t4, st); break;
+      case 3: e = launch_bucket<3>(d, t23, t4, st); break;
+      case 4: e = launch_bucket<4>(d, t23, t4, st); break;
+      case 5: e = launch_bucket<5>(d, t23, t4, st); break;
+      case 6: e = launch_bucket<6>(d, t23, t4, st); break;
+      default: e = launch_bucket<7>(d, t23, t4, st); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// A system with at least SOLO_FLOPS of contraction work (48 T N^5) fills the
+// chip with its own launches, and grouping it only shrinks its chunks: it
+// runs as a single-system chain.  Smaller systems share grouped launches.
+constexpr double SOLO_FLOPS = 1e12;
+inline bool batch_solo(const sb2_system& q) {
+  const double n = q.N;
+  return 48.0 * q.T * n * n * n * n * n >= SOLO_FLOPS;
+}
+
+// Systems grouped by ceil(N/16), in order of first appearance (solo systems excluded).
+std::vector<std::vector<sb2_system>> size_buckets(int nsys, const sb2_system* sys) {
+  std::vector<std::vector<sb2_system>> out;
+  std::vector<int> key;
+  for (int b = 0; b < nsys; ++b) {
+    if (batch_solo(sys[b])) continue;
+    const int k = (sys[b].N + 15) / 16;
+    size_t i = 0;
+    while (i < key.size() && key[i] != k) ++i;
+    if (i == key.size()) {
+      key.push_back(k);
+      out.emplace_back();
+    }
+    out[i].push_back(sys[b]);
+  }
+  return out;
 }
 
 hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const BatchPlan& bp, void* ws,
@@ -970,6 +1038,7 @@ hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const Ba
     }
     if (prec == SB2_FP64) e = group_chain<PK_F64>(refs, share, d_refs, s);
     else if (prec == SB2_FP32) e = group_chain<PK_F32>(refs, share, d_refs, s);
+    else if (bp.chunked) e = group_chain_h16(refs, share, d_refs, s);
     else e = group_chain<PK_H16>(refs, share, d_refs, s);
     if (e != hipSuccess) return e;
     for (size_t i = 0; i < refs.size(); ++i) {
@@ -1281,7 +1350,11 @@ size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec) {
   if (nsys < 1 || nsys > MAX_GROUP || !sys || !prec_ok(prec)) return 0;
   for (int i = 0; i < nsys; ++i)
     if (sys[i].N < 1 || sys[i].N > SB2_MAX_N || sys[i].T < 1 || sys[i].T > SB2_MAX_T) return 0;
-  return batch_plan(nsys, sys, prec).end;
+  size_t need = 0;
+  for (const auto& bk : size_buckets(nsys, sys)) need = std::max(need, batch_plan((int)bk.size(), bk.data(), prec).end);
+  for (int i = 0; i < nsys; ++i)
+    if (batch_solo(sys[i])) need = std::max(need, coll_plan(sys[i].N, sys[i].T, prec).end);
+  return need;
 }
 
 int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, size_t ws_bytes, void* stream) {
@@ -1292,10 +1365,29 @@ int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, s
     if (q.N < 1 || q.N > SB2_MAX_N || q.T < 1 || q.T > SB2_MAX_T) return SB2_ESHAPE;
     if (!q.v || !q.h || !q.rho_hist || !q.I_out || !finite_pos(q.dt)) return SB2_EINVAL;
   }
-  const BatchPlan bp = batch_plan(nsys, sys, prec);
-  if (ws_bytes < bp.end) return SB2_EWORKSPACE;
-  hipError_t e = collision_batched(nsys, sys, prec, bp, ws, reinterpret_cast<hipStream_t>(stream));
-  return e == hipSuccess ? SB2_OK : SB2_EHIP;
+  // systems of one 16-wide bucket of N share the rounds (and the whole
+  // intermediate budget); the buckets, then the solo systems, run one after
+  // the other in one enqueue
+  const auto buckets = size_buckets(nsys, sys);
+  std::vector<BatchPlan> plans;
+  for (const auto& bk : buckets) {
+    plans.push_back(batch_plan((int)bk.size(), bk.data(), prec));
+    if (ws_bytes < plans.back().end) return SB2_EWORKSPACE;
+  }
+  for (int b = 0; b < nsys; ++b)
+    if (batch_solo(sys[b]) && ws_bytes < coll_plan(sys[b].N, sys[b].T, prec).end) return SB2_EWORKSPACE;
+  for (size_t i = 0; i < buckets.size(); ++i) {
+    const hipError_t e = collision_batched((int)buckets[i].size(), buckets[i].data(), prec, plans[i], ws,
+                                           reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return SB2_EHIP;
+  }
+  for (int b = 0; b < nsys; ++b) {
+    if (!batch_solo(sys[b])) continue;
+    const sb2_system& q = sys[b];
+    const int st = sb2_collision(q.N, q.T, q.v, q.h, q.rho_hist, q.dt, q.I_out, nullptr, prec, ws, ws_bytes, stream);
+    if (st != SB2_OK) return st;
+  }
+  return SB2_OK;
 }
 
 }  // extern "C"

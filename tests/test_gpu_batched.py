@@ -69,3 +69,25 @@ def test_batched_graph_replay_matches_eager():
         for a, b in zip(outs, eager):
             assert torch.equal(a, b), rep
         _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between replays
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+def test_batched_mixed_solo_and_grouped(prec):
+    """A system with at least 1e12 flops of contraction work (here N = 64,
+    T = 20) runs on its own chain inside the batched call, the small ones in
+    grouped rounds; the small ones match the oracle and every result matches
+    the single-system call (itself checked against the oracle elsewhere)."""
+    from paper_1905_01180_amd import _lib
+    shapes = [(64, 20), (20, 5), (9, 4), (37, 3)]
+    assert 48 * 20 * 64 ** 5 >= 1e12 and all(48 * t * n ** 5 < 1e12 for n, t in shapes[1:])
+    sy = _systems(shapes)
+    print("case: batched mixed", prec, shapes, flush=True)
+    outs = _lib.sb2_collision_batched([d for _, d in sy], prec)
+    torch.cuda.synchronize()
+    for (s, d), got in zip(sy, outs):
+        g = got.cpu().numpy()
+        single = _lib.sb2_collision(*d, prec).cpu().numpy()
+        assert rel(g, single) < TOL[prec], (s.n, s.t, rel(g, single))
+        if s.n < 64:
+            want = o.collision(s.v, s.h, s.rho_hist, s.dt)
+            assert rel(g, want) < TOL[prec], (s.n, s.t, rel(g, want))
