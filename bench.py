@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="measure the 32-system batch (N 24..96, T 64..512): one grouped call vs 32 single calls")
     ap.add_argument("--autotune", action="store_true", help="run sb2_autotune for the workload before timing")
+    ap.add_argument("--small-batch", action="store_true",
+                    help="with --batched: 32 small systems (N 8..24, T 16..64) instead of N 24..96, T 64..512")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -250,7 +252,8 @@ def batched(args, torch, _lib, gen, dev):
     """32 systems of uneven size: the grouped entry point (eager and replayed
     from a captured HIP graph) against 32 single-system calls (eager and
     captured).  value = systems/s of the graph-replayed grouped call."""
-    systems = gen.make_batch(32, config_id=4)
+    rng_n, rng_t = ((8, 24), (16, 64)) if args.small_batch else ((24, 96), (64, 512))
+    systems = gen.make_batch(32, config_id=5 if args.small_batch else 4, n_range=rng_n, t_range=rng_t)
     data = [tuple(torch.from_numpy(x).to(dev) for x in (s.v, s.h, s.rho_hist)) + (s.dt,) for s in systems]
     flops = sum(48.0 * s.t * float(s.n) ** 5 for s in systems)
     prec = args.prec
@@ -320,11 +323,11 @@ def batched(args, torch, _lib, gen, dev):
     t_grp_g = time_graph(g_grp, args.steps)
     replay_equal = all(torch.equal(x, y) for x, y in zip(outs, b))
     out = {
-        "metric": "batched GKBA collision integrals: systems/s (32 systems, N 24..96, T 64..512)",
+        "metric": "batched GKBA collision integrals: systems/s (32 systems, N %d..%d, T %d..%d)" % (rng_n + rng_t),
         "value": 32.0 / t_grp_g, "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": 1e3 * t_grp_g, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": prec, "data": "synthetic",
-        "config": {"workload": "32 independent systems, N ~ U{24..96}, T ~ U{64..512}, one I(t) each",
+        "config": {"workload": "32 independent systems, N ~ U{%d..%d}, T ~ U{%d..%d}, one I(t) each" % (rng_n + rng_t),
                    "shapes": [[s.n, s.t] for s in systems]},
         "ms": {"single_calls_eager": 1e3 * t_seq, "single_calls_graph": 1e3 * t_seq_g,
                "grouped_eager": 1e3 * t_grp, "grouped_graph": 1e3 * t_grp_g},

@@ -935,7 +935,9 @@ hipError_t group_chain_h16(const std::vector<ChainRefs>& refs, const std::vector
     for (size_t i = 0; i < refs.size(); ++i) {
       if ((refs[i].N + 15) / 16 != nt) continue;
       const long long ntask = (long long)refs[i].ns * refs[i].N * refs[i].N;
-      long long nwg = (long long)(r23_wgs(refs[i].N, refs[i].prec) * share[i] / wsum + 0.5);
+      // grouped members are small systems: a generous workgroup count (more
+      // for fewer waves per workgroup) keeps the chip filled
+      long long nwg = (long long)(4.0 * r23_wgs(refs[i].N, refs[i].prec) * 7 / nt * share[i] / wsum + 0.5);
       if (nwg < 1) nwg = 1;
       if (nwg > ntask) nwg = ntask;
       t23.idx[t23.count] = t4.idx[t4.count] = (int)i;

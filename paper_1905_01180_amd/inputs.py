@@ -144,16 +144,17 @@ def make_config(config_id: int, **kw) -> System:
     return make_system(config_id=config_id, **CONFIGS[config_id], **kw)
 
 
-def batch_shapes(nsys: int = 32, config_id: int = 4) -> List[tuple]:
-    """(N_b, T_b) for the batched workload: N ~ U{24..96}, T ~ U{64..512}."""
+def batch_shapes(nsys: int = 32, config_id: int = 4, n_range=(24, 96), t_range=(64, 512)) -> List[tuple]:
+    """(N_b, T_b) for a batched workload: N ~ U{n_range}, T ~ U{t_range}
+    (defaults: the 32-system workload, N 24..96, T 64..512)."""
     g = rng(config_id, 0, _S_DIR)
-    ns = g.integers(24, 97, size=nsys)
-    ts = g.integers(64, 513, size=nsys)
+    ns = g.integers(n_range[0], n_range[1] + 1, size=nsys)
+    ts = g.integers(t_range[0], t_range[1] + 1, size=nsys)
     return [(int(a), int(b)) for a, b in zip(ns, ts)]
 
 
-def make_batch(nsys: int = 32, config_id: int = 4, shapes=None) -> List[System]:
-    shapes = shapes if shapes is not None else batch_shapes(nsys, config_id)
+def make_batch(nsys: int = 32, config_id: int = 4, shapes=None, n_range=(24, 96), t_range=(64, 512)) -> List[System]:
+    shapes = shapes if shapes is not None else batch_shapes(nsys, config_id, n_range, t_range)
     return [make_system(n, t, config_id=config_id, system_id=i + 1) for i, (n, t) in enumerate(shapes)]
 
 
