@@ -62,7 +62,7 @@ __device__ __forceinline__ int sub_member(const SubGroup& t, long long b) {
 }
 
 template <int NT>
-__global__ void __launch_bounds__(64 * NT) k_r23_group(const ChainRefs* __restrict__ refs, const SubGroup t) {
+__global__ void __launch_bounds__(64 * (NT + 1)) k_r23_group(const ChainRefs* __restrict__ refs, const SubGroup t) {
   const long long b = blockIdx.x;
   const int i = sub_member(t, b);
   const R23Args a = r23_args(refs[t.idx[i]]);

@@ -45,7 +45,7 @@ template <int FS>
 __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
   constexpr int NTH = 512, NCOL = 64, KS = 64, NKG = KS / 32;
   constexpr int FSP = (FS + 1) / 2 * 2, FH = FSP / 2;   // padded row fragments, per row half
-  constexpr int LP = KS + 8;                            // 144-byte rows: 16 mod 128
+  constexpr int LP = KS + 16;                           // 160-byte rows: 16 u bytes, u = 2 mod 4 (conflict-free fragment reads)
   static_assert((2 * 16 * FSP * (KS / 8)) % NTH == 0, "whole V' items per thread");
   constexpr int PV = 2 * 16 * FSP * (KS / 8) / NTH;     // V' items (hx8) per thread
   constexpr int PC = NCOL * KS / 2 / NTH;                // C loads (2 complex each) per thread

@@ -70,6 +70,18 @@ __device__ __forceinline__ int split_exp(float m, int& e, bool& ok) {
   return 14 - e;
 }
 
+// [x_re(4), x_im(4)] -> [x_im(4), -x_re(4)] (sign flips are exact)
+__device__ __forceinline__ hx8 swap_neg(hx8 x) {
+  typedef unsigned ux4 __attribute__((ext_vector_type(4)));
+  const ux4 u = __builtin_bit_cast(ux4, x);
+  ux4 r;
+  r[0] = u[2];
+  r[1] = u[3];
+  r[2] = u[0] ^ 0x80008000u;
+  r[3] = u[1] ^ 0x80008000u;
+  return __builtin_bit_cast(hx8, r);
+}
+
 __device__ __forceinline__ void split_h(float x, _Float16& hi, _Float16& lo) {
   hi = (_Float16)x;
   lo = (_Float16)(x - (float)hi);
@@ -77,112 +89,59 @@ __device__ __forceinline__ void split_h(float x, _Float16& hi, _Float16& lo) {
 
 template <int NT>
 struct R23Cfg {
-  static constexpr int NTH = 64 * NT;                 // threads (one wave per 16 columns p)
+  static constexpr int NCW = NT;                      // compute waves (one per 16 indices p)
+  static constexpr int NTH = 64 * (NT + 1);           // plus one producer wave
   static constexpr int KW = 32 * NT;                  // halves per row: NT chunks x 32 slots
-  // row pitch in halves, padded so consecutive rows start 16 bytes apart
-  // modulo 128 (conflict-free 16-byte fragment reads)
-  static constexpr int LP = KW + (((16 - (KW * 2) % 128) + 128) % 128) / 2;
+  // row pitch in halves: 16 u bytes with u = 2 mod 4 (KW is a multiple of 32),
+  // the pitches for which the 16-byte fragment reads of 16 rows x 4 lane
+  // groups are free of LDS bank conflicts on gfx950 (odd u halves the rate)
+  static constexpr int LP = KW + 16;
+  static constexpr int PI = NT;                       // producer items per lane: 16 ceil(N/4) <= 64 NT
+  static constexpr int PS = 3;                        // slabs in flight in the producer
+  static_assert(LP >= KW + 8, "row padding holds one 8-slot item");
+  static_assert((LP / 8) % 4 == 2, "conflict-free row pitch");
 };
 
 // Workgroup wg of nwg: tasks [ntask wg / nwg, ntask (wg + 1) / nwg).
+// Waves 0 .. NT-1 compute; wave NT (the producer) streams the A slabs: while
+// the compute waves multiply slab g it writes slab g + 1 (loaded PS slabs
+// earlier) into the free LDS buffer and loads slab g + 1 + PS.  The two roles run
+// separate loops (their registers do not overlap) with the same barrier
+// sequence: one barrier per slab, plus one after staging Gbt when NT = 1.
 template <int NT>
 __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
   using C_ = R23Cfg<NT>;
-  constexpr int KW = C_::KW, LP = C_::LP, NTH = C_::NTH;
+  constexpr int KW = C_::KW, LP = C_::LP, NTH = C_::NTH, PI = C_::PI;
   __shared__ __attribute__((aligned(16))) _Float16 sG[2][16 * NT][LP];   // Gbt slots: hi, lo
   __shared__ __attribute__((aligned(16))) _Float16 sA[2][2][16][LP];     // A slabs: buffer, hi/lo
-  __shared__ float red[NT];
+  __shared__ float red[NT + 1];
 
   const int N = a.N;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index (uniform)
   const int grp = lane >> 4, lr = lane & 15;
   const i64 nn = (i64)N * N;
   const i64 ntask = (i64)a.ns * nn;
   const i64 t0 = ntask * wg / nwg, t1 = ntask * (wg + 1) / nwg;
+  const i64 nslab = (t1 - t0) * NT;                   // slabs of this workgroup, in order
   // scales as exponents, so that no product of scales can overflow
   int ea, eg, egb;
   bool okA, okG, okGb;
   const int xA = split_exp(__uint_as_float(*a.amax), ea, okA);
   const int xG = split_exp(__uint_as_float(*a.gmax), eg, okG);
   const int xGb = split_exp(__uint_as_float(*a.gbmax), egb, okGb);
-  int nb = 0;                                         // 2 N <= 2^nb
-  while ((1 << nb) < 2 * N) ++nb;
-  // |Y| <= 2 N max|A| max|G| < 2^(ea + eg + nb)
-  const int xY = (okA && okG) ? 14 - (ea + eg + nb) : 0;
-  const float sAs = ldexpf(1.f, xA), sGs = ldexpf(1.f, xG), sGb = ldexpf(1.f, xGb);
-  const float fy = ldexpf(1.f, xY - xA - xG);        // accumulator -> Y 2^xY
-  const float unscale = ldexpf(1.f, -xGb - xY);
-  const int p = 16 * w + lr;                          // this lane's output column
+  const float sGb = ldexpf(1.f, xGb);
 
-  // slab item of this thread: row srow, q = 4 c4 .. 4 c4 + 3, slots 8 c4 .. 8 c4 + 7
-  // (16 ceil(N/4) <= 64 NT items: at most one per thread)
+  // slots past the last group of four q stay zero for the whole kernel
   const int nc4 = (N + 3) / 4;
-  const bool has_item = tid < 16 * nc4;
-  const int srow = has_item ? tid / nc4 : 0;
-  const int c4 = has_item ? tid - srow * nc4 : 0;
-  // slots past the last item stay zero for the whole kernel
   for (int L = tid; L < 2 * 2 * 16 * KW; L += NTH) {
     const int col = L % KW, rest = L / KW;
     if (col >= 8 * nc4) sA[rest / 32][(rest / 16) % 2][rest % 16][col] = (_Float16)0.f;
   }
 
-  // branch-free: out-of-range elements read a valid address and are zeroed
-  float2 pre[4];
-  auto load_slab = [&](i64 t, int c) {
-    const int s = 16 * c + srow;
-    const bool rowok = has_item && s < N;
-    const float2* src = reinterpret_cast<const float2*>(a.A) + t * nn + (rowok ? (i64)s * N + 4 * c4 : 0);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const bool ok = rowok && 4 * c4 + e < N;
-      const float2 v = src[ok ? e : 0];
-      pre[e] = ok ? v : make_float2(0.f, 0.f);
-    }
-  };
-  auto store_slab = [&](int buf) {
-    if (!has_item) return;
-    hx8 h, l;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      _Float16 x, y;
-      split_h(pre[e].x * sAs, x, y);
-      h[e] = x;
-      l[e] = y;
-      split_h(pre[e].y * sAs, x, y);
-      h[4 + e] = x;
-      l[4 + e] = y;
-    }
-    *reinterpret_cast<hx8*>(&sA[buf][0][srow][8 * c4]) = h;
-    *reinterpret_cast<hx8*>(&sA[buf][1][srow][8 * c4]) = l;
-  };
-
-  // ---- per-slice operands ----
-  // B operands of step 1 for chunk c: re = [G_re, -G_im], im = [G_im, G_re] at
-  // q = 16c + 4g + 0..3 of row p; hi and lo
-  hx8 bre_h[NT], bre_l[NT], bim_h[NT], bim_l[NT];
-  auto load_slice = [&](i64 b) {
-    const float2* G = reinterpret_cast<const float2*>(a.Gs) + b * nn;
-#pragma unroll
-    for (int c = 0; c < NT; ++c) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int q = 16 * c + 4 * grp + e;
-        float2 v = make_float2(0.f, 0.f);
-        if (p < N && q < N) v = G[(i64)p * N + q];
-        _Float16 rh, rl, ih, il;
-        split_h(v.x * sGs, rh, rl);
-        split_h(v.y * sGs, ih, il);
-        bre_h[c][e] = rh;
-        bre_l[c][e] = rl;
-        bre_h[c][4 + e] = -ih;
-        bre_l[c][4 + e] = -il;
-        bim_h[c][e] = ih;
-        bim_l[c][e] = il;
-        bim_h[c][4 + e] = rh;
-        bim_l[c][4 + e] = rl;
-      }
-    }
-    // Gbt_b: row r, slot 32 (s/16) + 8 ((s%16)/4) + (s%4) (+4 for the imaginary part)
+  // Gbt_b in LDS: row r, slot 32 (s/16) + 8 ((s%16)/4) + (s%4) (+4 for the
+  // imaginary part); every wave takes part
+  auto stage_gbt = [&](i64 b) {
     const float2* Gb = reinterpret_cast<const float2*>(a.GbT) + b * nn;
     for (int L = tid; L < 16 * NT * 16 * NT; L += NTH) {
       const int r = L / (16 * NT), s = L - r * (16 * NT);
@@ -193,124 +152,265 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
       split_h(v.y * sGb, sG[0][r][col + 4], sG[1][r][col + 4]);
     }
   };
-
-  fx4 cr[NT], ci[NT];
-#pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    cr[i] = vzero<fx4>();
-    ci[i] = vzero<fx4>();
-  }
-  // B operands of step 2 for the most recent slab: [Y_re, -Y_im] and
-  // [Y_im, Y_re] at s = 16c + 4g + i
-  hx8 pre_h, pre_l, pim_h, pim_l;
-  auto split_y = [&](const fx4& yr, const fx4& yi) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      _Float16 rh, rl, ih, il;
-      split_h(yr[i] * fy, rh, rl);
-      split_h(yi[i] * fy, ih, il);
-      pre_h[i] = rh;
-      pre_l[i] = rl;
-      pre_h[4 + i] = -ih;
-      pre_l[4 + i] = -il;
-      pim_h[i] = ih;
-      pim_l[i] = il;
-      pim_h[4 + i] = rh;
-      pim_l[4 + i] = rl;
-    }
-  };
-  // step 2 for slab cs: C[p][r] += Y[p][slab] Gbt[r][slab] with Y as the A
-  // operand (lane: row p, the slab's s slots) and Gbt as the B operand (lane:
-  // column r), so that the accumulators hold rows p = 16w + 4g + i and 16
-  // consecutive columns r = 16 rt + lane%16
-  auto step2 = [&](int cs) {
-#pragma unroll
-    for (int rt = 0; rt < NT; ++rt) {
-      const int row = 16 * rt + lr, col = 32 * cs + 8 * grp;
-      const hx8 gh = *reinterpret_cast<const hx8*>(&sG[0][row][col]);
-      const hx8 gl = *reinterpret_cast<const hx8*>(&sG[1][row][col]);
-      cr[rt] = mma3(pre_h, pre_l, gh, gl, cr[rt]);
-      ci[rt] = mma3(pim_h, pim_l, gh, gl, ci[rt]);
-    }
-  };
-
-  float mx = 0.f;
-  i64 cur_b = -1;
-  int buf = 0;
-  if (t0 < t1) load_slab(t0, 0);
-
+  // The slab sequence shared by both roles: body(t, b, c, g, buf) for slab g
+  // = chunk c of task t, after the barrier that publishes it in buffer buf.
+  auto for_slabs = [&](auto&& on_slice, auto&& body) {
+    i64 cur_b = -1, g = 0;
 #pragma unroll 1
-  for (i64 t = t0; t < t1; ++t) {
-    const i64 b = t / nn;
-    const i64 nj = t - b * nn;
-    const int n = (int)(nj / N), j = (int)(nj - (i64)(nj / N) * N);
-    if (b != cur_b) {                                 // uniform across the workgroup
-      __syncthreads();                                // every wave is done with the previous Gbt
-      load_slice(b);
-      cur_b = b;
-    }
+    for (i64 t = t0; t < t1; ++t) {
+      const i64 b = t / nn;
 #pragma unroll 1
-    for (int c = 0; c < NT; ++c) {                    // NT = ceil(N/16) slabs
-      store_slab(buf);
-      {                                               // prefetch the next slab (one call site: one register set)
-        const bool last = c + 1 == NT;
-        const i64 tn = last ? t + 1 : t;
-        if (tn < t1) load_slab(tn, last ? 0 : c + 1);
+      for (int c = 0; c < NT; ++c, ++g) {             // NT = ceil(N/16) slabs
+        __syncthreads();                              // slab g visible; the other buffer free
+        if (c == 0 && b != cur_b) {                   // uniform: all waves left the previous slice
+          on_slice(b);
+          stage_gbt(b);
+          cur_b = b;
+          if (NT == 1) __syncthreads();               // Gbt is read in this slab already
+        }
+        body(t, b, c, g, (int)(g & 1));
       }
-      __syncthreads();                                // slab c (and Gbt) visible; slab c-1's buffer free
+    }
+  };
 
+  if (w == NT) {
+    // ---- producer: item u of this lane = row prow[u] of the slab, q = 4 pc4[u] .. + 3
+    // (16 ceil(N/4) <= 64 NT items) ----
+    const float sAs = ldexpf(1.f, xA);
+    // items past 16 ceil(N/4) write zeros into the row padding (never read)
+    int prow[PI], pcol[PI], pq[PI];
+#pragma unroll
+    for (int u = 0; u < PI; ++u) {
+      const int L = lane + 64 * u;
+      const bool ok = L < 16 * nc4;
+      const int r = L / nc4;
+      prow[u] = ok ? r : 0;
+      pcol[u] = ok ? 8 * (L - r * nc4) : KW;
+      pq[u] = ok ? 4 * (L - r * nc4) : 1 << 20;
+    }
+    // PS register sets: slab x is held in set x % PS between its load and its
+    // store, so PS slabs are in flight while the compute waves multiply
+    constexpr int PS = C_::PS;
+    float2 pv[PS][PI][4];                             // 4 complex per item
+    // loads only clamp their addresses (registers untouched until stored, so
+    // the loads stay in flight); rows and q past N are zeroed when stored
+    auto p_load = [&](i64 g, float2 (&v)[PI][4]) {
+      const i64 t = t0 + g / NT;
+      const int c = (int)(g - (g / NT) * NT);
+      // uniform base and 32-bit byte offsets (N^2 elements per task)
+      const char* base = reinterpret_cast<const char*>(a.A) + (t * nn) * 8;
+#pragma unroll
+      for (int u = 0; u < PI; ++u) {
+        const unsigned ro = (unsigned)(min(16 * c + prow[u], N - 1) * N);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          v[u][e] = *reinterpret_cast<const float2*>(base + 8u * (ro + (unsigned)min(pq[u] + e, N - 1)));
+      }
+    };
+    auto p_store = [&](i64 g, int buf, const float2 (&v)[PI][4]) {
+      const int c = (int)(g - (g / NT) * NT);
+#pragma unroll
+      for (int u = 0; u < PI; ++u) {
+        const bool rowok = 16 * c + prow[u] < N;
+        hx8 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = rowok && pq[u] + e < N;
+          _Float16 xh, xl, yh, yl;
+          split_h(ok ? v[u][e].x * sAs : 0.f, xh, xl);
+          split_h(ok ? v[u][e].y * sAs : 0.f, yh, yl);
+          h[e] = xh;
+          l[e] = xl;
+          h[4 + e] = yh;
+          l[4 + e] = yl;
+        }
+        *reinterpret_cast<hx8*>(&sA[buf][0][prow[u]][pcol[u]]) = h;
+        *reinterpret_cast<hx8*>(&sA[buf][1][prow[u]][pcol[u]]) = l;
+      }
+    };
+    // prologue: slab 0 to buffer 0; slabs 1 .. PS in flight
+    if (nslab > 0) {
+      p_load(0, pv[0]);
+      p_store(0, 0, pv[0]);
+#pragma unroll
+      for (int k = 1; k <= PS; ++k)
+        if (k < nslab) p_load(k, pv[k % PS]);
+    }
+    // the same barrier sequence as the compute waves' slab loop, unrolled by
+    // PS so that every register set index is static
+    i64 cur_b = -1;
+#pragma unroll 1
+    for (i64 g0 = 0; g0 < nslab; g0 += PS) {
+#pragma unroll
+      for (int k = 0; k < PS; ++k) {
+        const i64 g = g0 + k;
+        if (g >= nslab) break;
+        __syncthreads();
+        const i64 t = t0 + g / NT;
+        const int c = (int)(g - (g / NT) * NT);
+        const i64 b = t / nn;
+        if (c == 0 && b != cur_b) {
+          stage_gbt(b);
+          cur_b = b;
+          if (NT == 1) __syncthreads();
+        }
+        const int ks = (k + 1) % PS;                  // set of slab g + 1 (g0 is a multiple of PS; static once unrolled)
+        if (g + 1 < nslab) p_store(g + 1, (int)((g + 1) & 1), pv[ks]);
+        if (g + 1 + PS < nslab) p_load(g + 1 + PS, pv[ks]);
+      }
+    }
+    if (lane == 0) red[w] = 0.f;
+  } else {
+    // ---- compute waves ----
+    int nb = 0;                                       // 2 N <= 2^nb
+    while ((1 << nb) < 2 * N) ++nb;
+    // |Y| <= 2 N max|A| max|G| < 2^(ea + eg + nb)
+    const int xY = (okA && okG) ? 14 - (ea + eg + nb) : 0;
+    const float sGs = ldexpf(1.f, xG);
+    const float fy = ldexpf(1.f, xY - xA - xG);      // accumulator -> Y 2^xY
+    const float unscale = ldexpf(1.f, -xGb - xY);
+    const int p = 16 * w + lr;                        // this lane's index p in step 1
+
+    // B operand of step 1 for chunk c: [G_re, -G_im] at q = 16c + 4g + 0..3
+    // of row p; hi and lo.  It serves both output parts: the real part pairs
+    // it with the A fragment [A_re, A_im], the imaginary part with the swapped
+    // fragment [A_im, -A_re].
+    hx8 bre_h[NT], bre_l[NT];
+    auto load_g = [&](i64 b) {
+      const float2* G = reinterpret_cast<const float2*>(a.Gs) + b * nn;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int q = 16 * c + 4 * grp + e;
+          float2 v = make_float2(0.f, 0.f);
+          if (p < N && q < N) v = G[(i64)p * N + q];
+          _Float16 rh, rl, ih, il;
+          split_h(v.x * sGs, rh, rl);
+          split_h(v.y * sGs, ih, il);
+          bre_h[c][e] = rh;
+          bre_l[c][e] = rl;
+          bre_h[c][4 + e] = -ih;
+          bre_l[c][4 + e] = -il;
+        }
+      }
+    };
+
+    fx4 cr[NT], ci[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      cr[i] = vzero<fx4>();
+      ci[i] = vzero<fx4>();
+    }
+    float mx = 0.f;
+    // B operands of step 2 for the most recent slab: [Y_re, -Y_im] and
+    // [Y_im, Y_re] at s = 16c + 4g + i
+    hx8 pre_h, pre_l, pim_h, pim_l;
+    auto split_y = [&](const fx4& yr, const fx4& yi) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        _Float16 rh, rl, ih, il;
+        split_h(yr[i] * fy, rh, rl);
+        split_h(yi[i] * fy, ih, il);
+        pre_h[i] = rh;
+        pre_l[i] = rl;
+        pre_h[4 + i] = -ih;
+        pre_l[4 + i] = -il;
+        pim_h[i] = ih;
+        pim_l[i] = il;
+        pim_h[4 + i] = rh;
+        pim_l[4 + i] = rl;
+      }
+    };
+    // step 2 for slab cs: C[p][r] += Y[p][slab] Gbt[r][slab] with Y as the A
+    // operand (lane: row p, the slab's s slots) and Gbt as the B operand
+    // (lane: column r), so that the accumulators hold rows p = 16w + 4g + i
+    // and 16 consecutive columns r = 16 rt + lane%16
+    auto read_g2 = [&](int cs, hx8 (&gh)[NT], hx8 (&gl)[NT]) {
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt) {
+        const int row = 16 * rt + lr, col = 32 * cs + 8 * grp;
+        gh[rt] = *reinterpret_cast<const hx8*>(&sG[0][row][col]);
+        gl[rt] = *reinterpret_cast<const hx8*>(&sG[1][row][col]);
+      }
+    };
+    auto step2 = [&](const hx8 (&gh)[NT], const hx8 (&gl)[NT]) {
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt) {
+        cr[rt] = mma3(pre_h, pre_l, gh[rt], gl[rt], cr[rt]);
+        ci[rt] = mma3(pim_h, pim_l, gh[rt], gl[rt], ci[rt]);
+      }
+    };
+
+    for_slabs(load_g, [&](i64 t, i64 b, int c, i64, int buf) {
+      // Gbt fragments of the previous slab's step 2, read ahead of step 1 so
+      // that their latency is hidden behind its products
+      hx8 gh[NT], gl[NT];
+      if (c > 0) read_g2(c - 1, gh, gl);
+      __builtin_amdgcn_sched_barrier(0);
       // step 1: Y^T rows 16c .. 16c+15, column p
       fx4 yr = vzero<fx4>(), yi = vzero<fx4>();
+      const _Float16* arow = &sA[buf][0][lr][8 * grp];
+      constexpr int PL = 16 * LP;                     // hi -> lo plane
+      hx8 ah = *reinterpret_cast<const hx8*>(arow), al = *reinterpret_cast<const hx8*>(arow + PL);
 #pragma unroll
       for (int qc = 0; qc < NT; ++qc) {
-        const int col = 32 * qc + 8 * grp;
-        const hx8 ah = *reinterpret_cast<const hx8*>(&sA[buf][0][lr][col]);
-        const hx8 al = *reinterpret_cast<const hx8*>(&sA[buf][1][lr][col]);
+        hx8 nh, nl;                                   // next chunk's fragments, in flight
+        if (qc + 1 < NT) {
+          nh = *reinterpret_cast<const hx8*>(arow + 32 * (qc + 1));
+          nl = *reinterpret_cast<const hx8*>(arow + PL + 32 * (qc + 1));
+        }
         yr = mma3(ah, al, bre_h[qc], bre_l[qc], yr);
-        yi = mma3(ah, al, bim_h[qc], bim_l[qc], yi);
+        yi = mma3(swap_neg(ah), swap_neg(al), bre_h[qc], bre_l[qc], yi);
+        if (qc + 1 < NT) {
+          ah = nh;
+          al = nl;
+        }
       }
       // step 2 of the previous slab: its products keep the matrix cores busy
       // while this slab's step-1 results drain and are split
-      if (c > 0) step2(c - 1);
+      if (c > 0) step2(gh, gl);
       split_y(yr, yi);
-      buf ^= 1;
-    }
-    step2(NT - 1);
-
-    // ---- store C_bjn[p][r], p = 16 w + 4 g + i, r = 16 rt + lane%16: each
-    // store instruction writes 16 consecutive r (128 bytes) of four rows p ----
-    const i64 blk = a.chunked ? ((i64)n * a.ns + b) * N + j : (b * N + j) * N + n;
-    float2* dst = reinterpret_cast<float2*>(a.C) + blk * nn;
+      if (c + 1 < NT) return;
+      read_g2(NT - 1, gh, gl);
+      step2(gh, gl);
+      // ---- store C_bjn[p][r], p = 16 w + 4 g + i, r = 16 rt + lane%16: each
+      // store instruction writes 16 consecutive r (128 bytes) of four rows p ----
+      const i64 nj = t - b * nn;
+      const int n = (int)(nj / N), j = (int)(nj - (i64)(nj / N) * N);
+      const i64 blk = a.chunked ? ((i64)n * a.ns + b) * N + j : (b * N + j) * N + n;
+      float2* dst = reinterpret_cast<float2*>(a.C) + blk * nn;
 #pragma unroll
-    for (int rt = 0; rt < NT; ++rt) {
-      const int r = 16 * rt + lr;
+      for (int rt = 0; rt < NT; ++rt) {
+        const int r = 16 * rt + lr;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int pp = 16 * w + 4 * grp + i;
-        const float re = cr[rt][i] * unscale, im = ci[rt][i] * unscale;
-        if (pp < N && r < N) {
-          dst[(i64)pp * N + r] = make_float2(re, im);
-          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        for (int i = 0; i < 4; ++i) {
+          const int pp = 16 * w + 4 * grp + i;
+          const float re = cr[rt][i] * unscale, im = ci[rt][i] * unscale;
+          if (pp < N && r < N) {
+            dst[(i64)pp * N + r] = make_float2(re, im);
+            mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+          }
         }
+        cr[rt] = vzero<fx4>();
+        ci[rt] = vzero<fx4>();
       }
-      cr[rt] = vzero<fx4>();
-      ci[rt] = vzero<fx4>();
-    }
+    });
+    mx = wave_max(mx);
+    if (lane == 0) red[w] = mx;
   }
   // block max -> recorded max |C|
-  mx = wave_max(mx);
-  if (lane == 0) red[w] = mx;
   __syncthreads();
   if (tid == 0) {
     float m = 0.f;
 #pragma unroll
-    for (int i = 0; i < NT; ++i) m = fmaxf(m, red[i]);
+    for (int i = 0; i <= NT; ++i) m = fmaxf(m, red[i]);
     if (m > 0.f) atomicMax(a.cmax, __float_as_uint(m));
   }
 }
 
 template <int NT>
-__global__ void __launch_bounds__(64 * NT) k_r23_h16(const R23Args a) {
+__global__ void __launch_bounds__(64 * (NT + 1)) k_r23_h16(const R23Args a) {
   r23_body<NT>(a, blockIdx.x, gridDim.x);
 }
 

@@ -333,7 +333,7 @@ template <int NT>
 hipError_t launch_r23_nt(const ChainRefs& r, int nwg, hipStream_t st) {
   const R23Args a = r23_args(r);
   StageTimer tm(1, st);
-  hipLaunchKernelGGL((k_r23_h16<NT>), dim3(nwg), dim3(64 * NT), 0, st, a);
+  hipLaunchKernelGGL((k_r23_h16<NT>), dim3(nwg), dim3(R23Cfg<NT>::NTH), 0, st, a);
   return hipGetLastError();
 }
 
@@ -908,7 +908,7 @@ hipError_t launch_bucket(const ChainRefs* d, const SubGroup& t23, const SubGroup
   hipError_t e;
   {
     StageTimer tm(1, st);
-    hipLaunchKernelGGL((k_r23_group<NT>), dim3((unsigned)t23.off[t23.count]), dim3(64 * NT), 0, st, d, t23);
+    hipLaunchKernelGGL((k_r23_group<NT>), dim3((unsigned)t23.off[t23.count]), dim3(R23Cfg<NT>::NTH), 0, st, d, t23);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   StageTimer tm(3, st);
