@@ -117,7 +117,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs& g, int bx, int by,
   constexpr int XW = 16 * FX, XT = XW * NW;
   constexpr int NPL = (H ? 2 : 1) * (SC ? 2 : 1);
   constexpr int LPB0 = KS * (int)sizeof(LT);
-  constexpr int PADB = ((16 - LPB0 % 128) + 128) % 128;
+  // 16-byte fragment reads (split float16): pitch 16 u bytes with u = 2 mod 4;
+  // element reads (float32, float64): pitch 16 mod 128 bytes
+  constexpr int PADB = H ? ((32 - LPB0 % 64) + 64) % 64 : ((16 - LPB0 % 128) + 128) % 128;
   constexpr int LP = KS + PADB / (int)sizeof(LT);
   constexpr int SE = SC ? 2 : 1, XE = XC ? 2 : 1;     // scalars per element
   static_assert(KS % KG == 0, "slab must hold whole K-groups");
@@ -530,7 +532,9 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
   constexpr int XT = 16 * NW;
   constexpr int NPL = (H ? 2 : 1) * (SC ? 2 : 1);
   constexpr int LPB0 = KS * (int)sizeof(LT);
-  constexpr int PADB = ((16 - LPB0 % 128) + 128) % 128;
+  // 16-byte fragment reads (split float16): pitch 16 u bytes with u = 2 mod 4;
+  // element reads (float32, float64): pitch 16 mod 128 bytes
+  constexpr int PADB = H ? ((32 - LPB0 % 64) + 64) % 64 : ((16 - LPB0 % 128) + 128) % 128;
   constexpr int LP = KS + PADB / (int)sizeof(LT);
   constexpr int SE = SC ? 2 : 1, XE = XC ? 2 : 1;
   static_assert(KS % KG == 0, "slab must hold whole K-groups");
