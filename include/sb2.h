@@ -67,7 +67,8 @@ typedef enum {
   SB2_OP_COLLISION = 1,
   SB2_OP_COLLISION_BACKWARD = 2,
   SB2_OP_RHO_STEP = 3,
-  SB2_OP_AUTOTUNE = 4
+  SB2_OP_AUTOTUNE = 4,
+  SB2_OP_PROPAGATE = 5
 } sb2_op;
 
 /* Largest basis size and history length accepted. */
@@ -123,6 +124,51 @@ int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_
 int sb2_collision_backward(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
                            const void* gI, double* gv, void* gh, void* grho,
                            int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* sb2_collision_prop -- sb2_collision with the propagators supplied by the
+ * caller: U_hist[k] = U(t, t_k), k = 0..T-1 (T x N x N complex), the HF
+ * propagators of Eq. 11 for any (time-dependent) effective one-body matrix.
+ * The GKBA functions (Eq. 10) and I(t) are formed from U_hist and rho_hist
+ * exactly as in sb2_collision; with U_hist[k] = exp(-i h (T-k) dt) the two
+ * calls agree up to the rounding of the propagators.  Workspace:
+ * sb2_workspace_size(SB2_OP_COLLISION, N, T, prec).  Errors: as sb2_collision. */
+int sb2_collision_prop(int N, int T, const double* v, const void* U_hist, const void* rho_hist, double dt,
+                       void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Terms of the equation of motion included by sb2_gkba_propagate. */
+typedef enum {
+  SB2_PROP_HF = 1,         /* Sigma_HF (Eq. 12) in the propagator and the commutator */
+  SB2_PROP_COLLISION = 2   /* the second-Born collision integral (Eq. 9)             */
+} sb2_prop_flags;
+
+/* sb2_gkba_propagate -- advance the GKBA density-matrix propagation (Sec. II,
+ * Eqs. 8-12; time-stepping without predictor-corrector as in Sec. IV) from
+ * step n0 to step n0 + nsteps, on the device, without host synchronisation.
+ * Time grid t_n = n dt.  Per step n:
+ *   h_HF(t_n)  = h + Sigma_HF(rho_n),   (Sigma_HF)_ij = sum_kl (2 v_iklj - v_ikjl) rho_lk
+ *   U_step     = exp(-i h_HF(t_n) dt)
+ *   I_n        = sb2_collision_prop over the past times t_0 .. t_{n-1} with
+ *                U(t_n, t_k) (I_0 = 0)
+ *   rho_{n+1}  = U_step rho_n U_step^dag - dt (I_n + I_n^dag)
+ *   U(t_{n+1}, t_k) = U_step U(t_n, t_k) for k < n,  U(t_{n+1}, t_n) = U_step,
+ * i.e. the time-ordered exponential of Eq. 11 with h_HF sampled at the start of
+ * each step.  Without SB2_PROP_HF the bare h is used; without
+ * SB2_PROP_COLLISION I_n = 0.
+ * State (caller-owned device memory, complex, row-major N x N slices):
+ *   rho_hist  capacity >= n0 + nsteps + 1 slices; rho_hist[0..n0] are read,
+ *             rho_hist[n0+1 .. n0+nsteps] are written;
+ *   U_hist    capacity >= n0 + nsteps slices; on entry U_hist[k] = U(t_n0, t_k)
+ *             for k < n0, on return U(t_{n0+nsteps}, t_k) for k < n0 + nsteps;
+ *   I_hist    optional (may be NULL), capacity >= n0 + nsteps slices;
+ *             I_hist[n] = I_n is written for n0 <= n < n0 + nsteps.
+ * The state after a call is the input of the next (checkpoint = these three
+ * arrays and n).  h: N x N complex, v: N^4 float64, as for sb2_collision.
+ * Workspace: sb2_workspace_size(SB2_OP_PROPAGATE, N, n0 + nsteps, prec).
+ * Errors: SB2_ESHAPE (N out of range, n0 < 0, nsteps < 1, n0 + nsteps >
+ * SB2_MAX_T), SB2_EINVAL (null pointer, dt not finite or <= 0, unknown prec
+ * or flags), SB2_EWORKSPACE.                                                  */
+int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
+                       void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream);
 
 /* One system of a batched collision-integral evaluation. */
 typedef struct {

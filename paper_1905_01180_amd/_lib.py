@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libsb2.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2}
-OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4}
+OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4, "propagate": 5}
+PROP_HF, PROP_COLLISION = 1, 2
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
           -5: "SB2_EUNSUPPORTED"}
 
@@ -71,6 +72,10 @@ def lib() -> ctypes.CDLL:
         L.sb2_set_tuning.argtypes = [_i, _i, _i, _i, _i]
         L.sb2_rho_step.restype = _i
         L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
+        L.sb2_collision_prop.restype = _i
+        L.sb2_collision_prop.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
+        L.sb2_gkba_propagate.restype = _i
+        L.sb2_gkba_propagate.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         _lib = L
         return L
 
@@ -162,6 +167,49 @@ def sb2_collision(v: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: 
     _call("sb2_collision", n, t, v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt), out.data_ptr(),
           sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(), _stream(v.device))
     return (out, sig) if return_sigma else out
+
+
+def sb2_collision_prop(v: torch.Tensor, u_hist: torch.Tensor, rho_hist: torch.Tensor, dt: float, prec="fp64",
+                       return_sigma: bool = False):
+    """I_ns(t) (N, N) from given propagators u_hist[k] = U(t, t_k) (T, N, N)."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(u_hist, "u_hist", torch.complex128, (t, n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    p = _prec(prec)
+    ws = workspace(sb2_workspace_size("collision", n, t, p), v.device)
+    out = torch.empty((n, n), dtype=torch.complex128, device=v.device)
+    sig = torch.empty((2, t, n, n), dtype=torch.complex128, device=v.device) if return_sigma else None
+    _call("sb2_collision_prop", n, t, v.data_ptr(), u_hist.data_ptr(), rho_hist.data_ptr(), float(dt),
+          out.data_ptr(), sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(),
+          _stream(v.device))
+    return (out, sig) if return_sigma else out
+
+
+def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, prec="fp64", hf: bool = True,
+                       collision: bool = True, i_hist=None):
+    """Advance the propagation state in place from step n0 to n0 + nsteps.
+
+    rho_hist (C, N, N) with C >= n0 + nsteps + 1, u_hist and i_hist (C', N, N)
+    with C' >= n0 + nsteps (i_hist optional); all complex128 on the device.
+    """
+    n = h.shape[0]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (rho_hist.shape[0], n, n))
+    _check(u_hist, "u_hist", torch.complex128, (u_hist.shape[0], n, n))
+    if rho_hist.shape[0] < n0 + nsteps + 1 or u_hist.shape[0] < max(n0 + nsteps, 1):
+        raise ValueError("rho_hist / u_hist capacity too small for n0 + nsteps")
+    if i_hist is not None:
+        _check(i_hist, "i_hist", torch.complex128, (i_hist.shape[0], n, n))
+        if i_hist.shape[0] < n0 + nsteps:
+            raise ValueError("i_hist capacity too small for n0 + nsteps")
+    p = _prec(prec)
+    ws = workspace(sb2_workspace_size("propagate", n, n0 + nsteps, p), v.device)
+    flags = (PROP_HF if hf else 0) | (PROP_COLLISION if collision else 0)
+    _call("sb2_gkba_propagate", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
+          u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt), flags, p,
+          ws.data_ptr(), ws.numel(), _stream(v.device))
 
 
 def sb2_collision_backward(v, h, rho_hist, dt, grad_i, prec="fp64"):

@@ -456,6 +456,34 @@ __global__ void k_rho_finish(int N, const cplx* __restrict__ Y, const cplx* __re
   out[e] = Y[e] - (a + b) * dt;
 }
 
+// Effective one-body matrix out = h + Sigma_HF(rho) (with_hf = 0: out = h),
+// Eq. 12: (Sigma_HF)_ij = sum_kl (2 v_iklj - v_ikjl) rho_lk, float64.
+// Workgroup i (N <= SIGMA_HF_THREADS), thread j; for every k the column
+// rho[:, k] is staged in LDS and the (i, k) slab v[i][k][:][:] is read once
+// per term: v_iklj along the row l (coalesced over j), v_ikjl along row j.
+constexpr int SIGMA_HF_THREADS = 128;
+__global__ void __launch_bounds__(SIGMA_HF_THREADS)
+k_sigma_hf(int N, const double* __restrict__ v, const cplx* __restrict__ rho, const cplx* __restrict__ h,
+           int with_hf, cplx* __restrict__ out) {
+  __shared__ cplx col[SIGMA_HF_THREADS];
+  const int i = blockIdx.x, j = threadIdx.x;
+  const i64 nn = (i64)N * N;
+  cplx acc = mk(0.0, 0.0);
+  if (with_hf) {
+    for (int k = 0; k < N; ++k) {
+      __syncthreads();
+      if (j < N) col[j] = rho[(i64)j * N + k];
+      __syncthreads();
+      if (j < N) {
+        const double* slab = v + ((i64)i * N + k) * nn;   // slab[l][m] = v[i][k][l][m]
+        const double* row = slab + (i64)j * N;            // v_ikjl over l
+        for (int l = 0; l < N; ++l) acc += col[l] * (2.0 * slab[(i64)l * N + j] - row[l]);
+      }
+    }
+  }
+  if (j < N) out[(i64)i * N + j] = h[(i64)i * N + j] + acc;
+}
+
 // x <- (a + i b) x
 __global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;

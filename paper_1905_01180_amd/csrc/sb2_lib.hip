@@ -220,6 +220,29 @@ size_t tune_bytes(int N, int T, int prec) {
 
 size_t rho_plan(int N) { return 4 * al((size_t)N * N * C128); }
 
+// Workspace of a propagation that ends with n_end + 1 densities: the
+// collision evaluations (at most n_end - 1 past times; the collision plan
+// grows with T) followed by the step's own N x N matrices and the staging
+// area of the propagator-history update.
+struct PropPlan {
+  size_t heff, ustep, I, T1, ex1, ex2, tmp, end;
+};
+PropPlan prop_plan(int N, int n_end, int prec) {
+  PropPlan p;
+  const size_t m = al((size_t)N * N * C128);
+  size_t o = n_end >= 2 ? al(coll_plan(N, n_end - 1, prec).end) : 0;
+  p.heff = o; o += m;
+  p.ustep = o; o += m;
+  p.I = o; o += m;
+  p.T1 = o; o += m;
+  p.ex1 = o; o += m;
+  p.ex2 = o; o += m;
+  p.tmp = o; o += al((size_t)(n_end > 1 ? n_end - 1 : 1) * N * N * C128);
+  p.end = o;
+  return p;
+}
+
+
 inline char* at(void* ws, size_t off) { return reinterpret_cast<char*>(ws) + off; }
 
 // ---------------------------------------------------------------------------
@@ -1140,6 +1163,9 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
     case SB2_OP_AUTOTUNE:
       if (T < 1 || T > SB2_MAX_T) return 0;
       return tune_bytes(N, T, prec);
+    case SB2_OP_PROPAGATE:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return prop_plan(N, T, prec).end;
     default:
       return 0;
   }
@@ -1157,15 +1183,12 @@ int sb2_sigma(int N, int B, const double* v, const void* Gl, const void* Gg, voi
   return e == hipSuccess ? SB2_OK : SB2_EHIP;
 }
 
-int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, void* I_out,
-                  void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
-  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
-  if (!v || !h || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
-  const CollPlan c = coll_plan(N, T, prec);
-  if (ws_bytes < c.end) return SB2_EWORKSPACE;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+// Collision integral from given propagators U[k] = U(t, t_k), k < T (Eq. 10
+// with Eq. 11's propagators supplied): X_k = U_k rho_k, Y_k = rho_k U_k^dag,
+// the four GKBA functions, the self-energy chain and the k-sum.
+hipError_t collision_core(int N, int T, const double* v, const cplx* U, const void* rho_hist, double dt,
+                          cplx* I_out, cplx* Sigma_out, int prec, const CollPlan& c, void* ws, hipStream_t s) {
   const i64 nn = (i64)N * N;
-  cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
   cplx* X = reinterpret_cast<cplx*>(at(ws, c.X));
   cplx* Y = reinterpret_cast<cplx*>(at(ws, c.Y));
   cplx* Gl = reinterpret_cast<cplx*>(at(ws, c.Gl));
@@ -1175,34 +1198,30 @@ int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_
   cplx* Sl = reinterpret_cast<cplx*>(at(ws, c.Sl));
   cplx* Sg = reinterpret_cast<cplx*>(at(ws, c.Sg));
   cplx* terms = reinterpret_cast<cplx*>(at(ws, c.terms));
-
+  hipError_t e;
   GemmArgs g;
   {
-  StageTimer tm(5, s);
-  if (propagators(N, T, h, dt, U, reinterpret_cast<cplx*>(at(ws, c.ex1)), reinterpret_cast<cplx*>(at(ws, c.ex2)),
-                  s) != hipSuccess)
-    return SB2_EHIP;
-  // X_k = U_k rho_k ; Y_k = rho_k U_k^dag
-  g = gdef();
-  g.M = N; g.N = N; g.K = N;
-  g.A = U; g.sAm = N; g.sAk = 1; g.sAbh = nn;
-  g.B = rho_hist; g.sBk = N; g.sBn = 1; g.sBbh = nn;
-  g.C = X; g.sCm = N; g.sCn = 1; g.sCbh = nn;
-  SB2_TRY(zgemm(g, T, s));
-  g = gdef();
-  g.M = N; g.N = N; g.K = N;
-  g.A = rho_hist; g.sAm = N; g.sAk = 1; g.sAbh = nn;
-  g.B = U; g.sBk = 1; g.sBn = N; g.sBbh = nn; g.conjB = 1;
-  g.C = Y; g.sCm = N; g.sCn = 1; g.sCbh = nn;
-  SB2_TRY(zgemm(g, T, s));
-  hipLaunchKernelGGL(k_gkba, dim3(blocks((long long)T * nn, 256)), dim3(256), 0, s, N, T, U, X, Y, Gl, Gg, Glb,
-                     Ggb);
-  SB2_TRY(hipGetLastError());
+    StageTimer tm(5, s);
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = U; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+    g.B = rho_hist; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+    g.C = X; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = rho_hist; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+    g.B = U; g.sBk = 1; g.sBn = N; g.sBbh = nn; g.conjB = 1;
+    g.C = Y; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gkba, dim3(blocks((long long)T * nn, 256)), dim3(256), 0, s, N, T, U, X, Y, Gl, Gg, Glb,
+                       Ggb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
 
-  cplx* Ol = Sigma_out ? reinterpret_cast<cplx*>(Sigma_out) : nullptr;
+  cplx* Ol = Sigma_out;
   cplx* Og = Sigma_out ? Ol + (i64)T * nn : nullptr;
-  SB2_TRY(sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s));
+  if ((e = sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s)) != hipSuccess) return e;
 
   // terms_k = Sigma^>_k G^<(t_k,t) - Sigma^<_k G^>(t_k,t)
   StageTimer tm(7, s);
@@ -1211,12 +1230,109 @@ int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_
   g.A = Sg; g.sAm = N; g.sAk = 1; g.sAbh = nn;
   g.B = Glb; g.sBk = N; g.sBn = 1; g.sBbh = nn;
   g.C = terms; g.sCm = N; g.sCn = 1; g.sCbh = nn;
-  SB2_TRY(zgemm(g, T, s));
+  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
   g.A = Sl; g.B = Ggb; g.alpha_re = -1.0; g.beta1 = 1;
-  SB2_TRY(zgemm(g, T, s));
-  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt,
-                     reinterpret_cast<cplx*>(I_out));
-  SB2_TRY(hipGetLastError());
+  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt, I_out);
+  return hipGetLastError();
+}
+
+int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, void* I_out,
+                  void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  const CollPlan c = coll_plan(N, T, prec);
+  if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
+  {
+    StageTimer tm(5, s);
+    SB2_TRY(propagators(N, T, h, dt, U, reinterpret_cast<cplx*>(at(ws, c.ex1)),
+                        reinterpret_cast<cplx*>(at(ws, c.ex2)), s));
+  }
+  SB2_TRY(collision_core(N, T, v, U, rho_hist, dt, reinterpret_cast<cplx*>(I_out),
+                         reinterpret_cast<cplx*>(Sigma_out), prec, c, ws, s));
+  return SB2_OK;
+}
+
+int sb2_collision_prop(int N, int T, const double* v, const void* U_hist, const void* rho_hist, double dt,
+                       void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !U_hist || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  const CollPlan c = coll_plan(N, T, prec);
+  if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  SB2_TRY(collision_core(N, T, v, reinterpret_cast<const cplx*>(U_hist), rho_hist, dt,
+                         reinterpret_cast<cplx*>(I_out), reinterpret_cast<cplx*>(Sigma_out), prec, c, ws,
+                         reinterpret_cast<hipStream_t>(stream)));
+  return SB2_OK;
+}
+
+int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
+                       void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !U_hist || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
+  const int n_end = n0 + nsteps;
+  const PropPlan p = prop_plan(N, n_end, prec);
+  if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const i64 nn = (i64)N * N;
+  const size_t mb = (size_t)nn * C128;
+  cplx* rho = reinterpret_cast<cplx*>(rho_hist);
+  cplx* U = reinterpret_cast<cplx*>(U_hist);
+  cplx* heff = reinterpret_cast<cplx*>(at(ws, p.heff));
+  cplx* ustep = reinterpret_cast<cplx*>(at(ws, p.ustep));
+  cplx* I = reinterpret_cast<cplx*>(at(ws, p.I));
+  cplx* T1 = reinterpret_cast<cplx*>(at(ws, p.T1));
+  cplx* ex1 = reinterpret_cast<cplx*>(at(ws, p.ex1));
+  cplx* ex2 = reinterpret_cast<cplx*>(at(ws, p.ex2));
+  cplx* tmp = reinterpret_cast<cplx*>(at(ws, p.tmp));
+  for (int n = n0; n < n_end; ++n) {
+    cplx* rho_n = rho + (i64)n * nn;
+    // h_HF(t_n) = h + Sigma_HF(rho_n) (Eq. 12), U_step = exp(-i h_HF dt) (Eq. 11)
+    hipLaunchKernelGGL(k_sigma_hf, dim3(N), dim3(SIGMA_HF_THREADS), 0, s, N, v, rho_n,
+                       reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff);
+    SB2_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, heff, 0.0, -dt, ustep, ex1, ex2);
+    SB2_TRY(hipGetLastError());
+    // I_ns(t_n) over the past times t_0 .. t_{n-1} (Eq. 9)
+    if ((flags & SB2_PROP_COLLISION) && n > 0) {
+      const CollPlan c = coll_plan(N, n, prec);
+      SB2_TRY(collision_core(N, n, v, U, rho, dt, I, nullptr, prec, c, ws, s));
+    } else {
+      hipLaunchKernelGGL(k_fill_u32, dim3(blocks(4 * nn, 256)), dim3(256), 0, s, reinterpret_cast<unsigned*>(I),
+                         (int)(4 * nn), 0u);
+      SB2_TRY(hipGetLastError());
+    }
+    if (I_hist) SB2_TRY(hipMemcpyAsync(reinterpret_cast<cplx*>(I_hist) + (i64)n * nn, I, mb,
+                                       hipMemcpyDeviceToDevice, s));
+    // rho_{n+1} = U_step rho_n U_step^dag - dt (I + I^dag) (Eq. 8, exponential Euler)
+    GemmArgs g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = ustep; g.sAm = N; g.sAk = 1;
+    g.B = rho_n; g.sBk = N; g.sBn = 1;
+    g.C = T1; g.sCm = N; g.sCn = 1;
+    SB2_TRY(zgemm(g, 1, s));
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = T1; g.sAm = N; g.sAk = 1;
+    g.B = ustep; g.sBk = 1; g.sBn = N; g.conjB = 1;
+    g.C = ex1; g.sCm = N; g.sCn = 1;
+    SB2_TRY(zgemm(g, 1, s));
+    hipLaunchKernelGGL(k_rho_finish, dim3(blocks(nn, 256)), dim3(256), 0, s, N, ex1, I, dt, rho_n + nn);
+    SB2_TRY(hipGetLastError());
+    // U(t_{n+1}, t_k) = U_step U(t_n, t_k) for k < n, U(t_{n+1}, t_n) = U_step
+    if (n > 0) {
+      g = gdef();
+      g.M = N; g.N = N; g.K = N;
+      g.A = ustep; g.sAm = N; g.sAk = 1; g.sAbh = 0;
+      g.B = U; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+      g.C = tmp; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+      SB2_TRY(zgemm(g, n, s));
+      SB2_TRY(hipMemcpyAsync(U, tmp, (size_t)n * mb, hipMemcpyDeviceToDevice, s));
+    }
+    SB2_TRY(hipMemcpyAsync(U + (i64)n * nn, ustep, mb, hipMemcpyDeviceToDevice, s));
+  }
   return SB2_OK;
 }
 

@@ -1,0 +1,97 @@
+"""Host-side checks of the propagation entry points and the checkpoint format
+(no GPU: argument validation happens before anything is enqueued, and the
+checkpoint files are plain numpy archives)."""
+import numpy as np
+import pytest
+
+from paper_1905_01180_amd import _lib
+from paper_1905_01180_amd import driver
+
+FAKE = 0x1000   # never dereferenced: validation fails first
+BIG = 1 << 40
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_new_functions_are_declared_and_exported(L):
+    names = set(_lib.header_functions())
+    assert {"sb2_collision_prop", "sb2_gkba_propagate"} <= names
+    for n in ("sb2_collision_prop", "sb2_gkba_propagate"):
+        assert hasattr(L, n)
+
+
+def test_propagate_workspace_covers_every_collision(L):
+    ws = _lib.sb2_workspace_size
+    for prec in ("fp64", "fp32", "fp16x3"):
+        for n in (1, 7, 33, 100):
+            prev = 0
+            for t in (1, 2, 3, 9, 40, 41, 200):
+                c = ws("collision", n, t, prec)
+                assert c >= prev                     # the collision plan grows with T
+                prev = c
+                # a propagation ending at step t + 1 evaluates collisions up to T = t
+                assert ws("propagate", n, t + 1, prec) >= c
+    assert ws("propagate", 10, 0, "fp64") == 0
+    assert ws("propagate", 0, 5, "fp64") == 0
+
+
+def test_propagate_argument_errors(L):
+    p = L.sb2_gkba_propagate
+    args = lambda **kw: [kw.get("N", 8), kw.get("n0", 0), kw.get("nsteps", 3), kw.get("v", FAKE), kw.get("h", FAKE),
+                         kw.get("rho", FAKE), kw.get("u", FAKE), None, kw.get("dt", 0.05), kw.get("flags", 3),
+                         kw.get("prec", 0), FAKE, kw.get("ws", BIG), None]
+    assert p(*args(N=0)) == -2
+    assert p(*args(N=129)) == -2
+    assert p(*args(n0=-1)) == -2
+    assert p(*args(nsteps=0)) == -2
+    assert p(*args(n0=65536, nsteps=1)) == -2
+    assert p(*args(v=None)) == -1
+    assert p(*args(rho=None)) == -1
+    assert p(*args(u=None)) == -1
+    assert p(*args(dt=0.0)) == -1
+    assert p(*args(dt=float("inf"))) == -1
+    assert p(*args(flags=4)) == -1
+    assert p(*args(prec=7)) == -1
+    assert p(*args(ws=64)) == -3
+    c = L.sb2_collision_prop
+    assert c(8, 0, FAKE, FAKE, FAKE, 0.05, FAKE, None, 0, FAKE, BIG, None) == -2
+    assert c(8, 4, FAKE, None, FAKE, 0.05, FAKE, None, 0, FAKE, BIG, None) == -1
+    assert c(8, 4, FAKE, FAKE, FAKE, 0.05, FAKE, None, 0, FAKE, 64, None) == -3
+
+
+def _state(n, nb=3, seed=0):
+    g = np.random.default_rng(seed)
+    c = lambda *s: g.standard_normal(s) + 1j * g.standard_normal(s)
+    return {"n": n, "dt": 0.05, "prec": "fp16x3", "hf": True, "collision": False,
+            "rho": c(n + 1, nb, nb), "u": c(n, nb, nb), "i": c(n, nb, nb)}
+
+
+def test_checkpoint_round_trip(tmp_path):
+    for n in (0, 1, 5):
+        st = _state(n, seed=n)
+        path = str(tmp_path / f"s{n}.npz")
+        driver.save_state(path, st)
+        back = driver.load_state(path)
+        for k in ("n", "dt", "prec", "hf", "collision"):
+            assert back[k] == st[k]
+        for k in ("rho", "u", "i"):
+            assert back[k].dtype == np.complex128
+            assert np.array_equal(back[k], st[k])
+
+
+def test_checkpoint_rejects_inconsistent_states(tmp_path):
+    st = _state(3)
+    st["u"] = st["u"][:2]
+    with pytest.raises(ValueError):
+        driver.save_state(str(tmp_path / "bad.npz"), st)
+    st = _state(3)
+    st["prec"] = "fp8"
+    with pytest.raises(ValueError):
+        driver.check_state(st)
+    st = _state(2)
+    st["dt"] = -1.0
+    with pytest.raises(ValueError):
+        driver.check_state(st)
