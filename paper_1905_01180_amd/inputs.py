@@ -88,6 +88,11 @@ def density_matrix(n: int, g: np.random.Generator) -> np.ndarray:
     return 0.5 * (rho + rho.conj().T)
 
 
+def unitary_path(hr: np.ndarray, taus: np.ndarray) -> np.ndarray:
+    """exp(-i hr tau) for every tau (a smooth path of unitaries, for synthetic states)."""
+    return _unitary_path(hr, np.asarray(taus, dtype=np.float64))
+
+
 def _unitary_path(hr: np.ndarray, taus: np.ndarray) -> np.ndarray:
     e, p = np.linalg.eigh(hr)
     ph = np.exp(-1j * e[None, :] * taus[:, None])                # (K, n)
