@@ -68,7 +68,9 @@ typedef enum {
   SB2_OP_COLLISION_BACKWARD = 2,
   SB2_OP_RHO_STEP = 3,
   SB2_OP_AUTOTUNE = 4,
-  SB2_OP_PROPAGATE = 5
+  SB2_OP_PROPAGATE = 5,
+  SB2_OP_COLLISION_DIAGONAL = 6,
+  SB2_OP_COLLISION_SYMMETRIC = 7
 } sb2_op;
 
 /* Largest basis size and history length accepted. */
@@ -134,6 +136,26 @@ int sb2_collision_backward(int N, int T, const double* v, const void* h, const v
  * sb2_workspace_size(SB2_OP_COLLISION, N, T, prec).  Errors: as sb2_collision. */
 int sb2_collision_prop(int N, int T, const double* v, const void* U_hist, const void* rho_hist, double dt,
                        void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Special interaction vertices of Sec. III. */
+typedef enum {
+  SB2_VERTEX_DIAGONAL = 1,   /* v_ijkl = U_i d_ij d_ik d_il (Hubbard-like), parameter U: N float64  */
+  SB2_VERTEX_SYMMETRIC = 2   /* v_ijkl = V_ij d_il d_jk (density-density), parameter V: N x N float64 */
+} sb2_vertex;
+
+/* sb2_collision_vertex -- sb2_collision for a special vertex, float64 throughout.
+ * The GKBA functions and the sum over past times are those of sb2_collision
+ * (Eqs. 9-11); the self-energy is
+ *   diagonal basis (Eq. 14):  Sigma_ij = U_i U_j G_ij Gbar_ji G_ij                         O(N^2)
+ *   symmetric basis (Eq. 16): Sigma = 2 G o [(V x {[V x (Gbar^T o G)]}^T)^T]   (Eq. 17, bubble)
+ *                             - sum_kl V_ik V_jl G_il Gbar_lk G_kj               (exchange) O(N^4)
+ * with G, Gbar as in sb2_collision.  vparam: U (N float64) or V (N x N
+ * float64, row-major, V[i][j] = V_ij), device pointer.  h, rho_hist, I_out,
+ * Sigma_out as for sb2_collision.  Workspace: sb2_workspace_size(
+ * SB2_OP_COLLISION_DIAGONAL or SB2_OP_COLLISION_SYMMETRIC, N, T, any prec).
+ * Errors: as sb2_collision; SB2_EINVAL for an unknown vertex.                */
+int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const void* h, const void* rho_hist,
+                         double dt, void* I_out, void* Sigma_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Terms of the equation of motion included by sb2_gkba_propagate. */
 typedef enum {

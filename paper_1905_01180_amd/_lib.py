@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(HERE, "libsb2.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2}
-OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4, "propagate": 5}
+OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4, "propagate": 5,
+       "collision_diagonal": 6, "collision_symmetric": 7}
+VERTICES = {"diagonal": 1, "symmetric": 2}
 PROP_HF, PROP_COLLISION = 1, 2
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
           -5: "SB2_EUNSUPPORTED"}
@@ -74,6 +76,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
         L.sb2_collision_prop.restype = _i
         L.sb2_collision_prop.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
+        L.sb2_collision_vertex.restype = _i
+        L.sb2_collision_vertex.argtypes = [_i, _i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _sz, _vp]
         L.sb2_gkba_propagate.restype = _i
         L.sb2_gkba_propagate.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         _lib = L
@@ -183,6 +187,25 @@ def sb2_collision_prop(v: torch.Tensor, u_hist: torch.Tensor, rho_hist: torch.Te
     _call("sb2_collision_prop", n, t, v.data_ptr(), u_hist.data_ptr(), rho_hist.data_ptr(), float(dt),
           out.data_ptr(), sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(),
           _stream(v.device))
+    return (out, sig) if return_sigma else out
+
+
+def sb2_collision_vertex(vertex: str, param: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: float,
+                         return_sigma: bool = False):
+    """I_ns(t) (N, N) for a special vertex: 'diagonal' (param U, (N,)) or
+    'symmetric' (param V, (N, N)); float64 throughout."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    if vertex not in VERTICES:
+        raise ValueError(f"vertex must be one of {sorted(VERTICES)}, got {vertex!r}")
+    _check(param, "param", torch.float64, (n,) if vertex == "diagonal" else (n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    ws = workspace(sb2_workspace_size("collision_" + vertex, n, t, 0), h.device)
+    out = torch.empty((n, n), dtype=torch.complex128, device=h.device)
+    sig = torch.empty((2, t, n, n), dtype=torch.complex128, device=h.device) if return_sigma else None
+    _call("sb2_collision_vertex", n, t, VERTICES[vertex], param.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
+          float(dt), out.data_ptr(), sig.data_ptr() if sig is not None else None, ws.data_ptr(), ws.numel(),
+          _stream(h.device))
     return (out, sig) if return_sigma else out
 
 

@@ -484,6 +484,75 @@ k_sigma_hf(int N, const double* __restrict__ v, const cplx* __restrict__ rho, co
   if (j < N) out[(i64)i * N + j] = h[(i64)i * N + j] + acc;
 }
 
+// ---------------------------------------------------------------------------
+// Self-energy of the special vertices (Sec. III A, III B), float64, for T
+// slices of one kind: G[k] = G(t, t_k) and Gb[k] = Gbar (the opposite-kind
+// function at (t_k, t)), row-major N x N each.
+// ---------------------------------------------------------------------------
+
+// Diagonal basis, Eq. 14: S_ij = U_i U_j G_ij Gb_ji G_ij.
+__global__ void k_sigma_diag(int N, int T, const double* __restrict__ u, const cplx* __restrict__ G,
+                             const cplx* __restrict__ Gb, cplx* __restrict__ S) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn * T) return;
+  const i64 k = e / nn;
+  const int r = (int)(e - k * nn);
+  const int i = r / N, j = r - (r / N) * N;
+  const cplx g = G[e];
+  S[e] = cmul(cmul(g, Gb[k * nn + (i64)j * N + i]), g) * (u[i] * u[j]);
+}
+
+// Symmetric basis, bubble operand of Eq. 17: P_ab = Gb_ba G_ab.
+__global__ void k_sym_bubble_in(int N, int T, const cplx* __restrict__ G, const cplx* __restrict__ Gb,
+                                cplx* __restrict__ P) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn * T) return;
+  const i64 k = e / nn;
+  const int r = (int)(e - k * nn);
+  const int a = r / N, b = r - (r / N) * N;
+  P[e] = cmul(Gb[k * nn + (i64)b * N + a], G[e]);
+}
+
+// Symmetric basis, exchange operand: A[k][i][l][m] = G_il Gb_lm V_im, so that
+// (A[k][i] x G)_lj summed against V_jl over l gives the exchange term
+// sum_{m,l} V_im V_jl G_il Gb_lm G_mj of Eq. 16.
+__global__ void k_sym_exch_in(int N, int T, const double* __restrict__ V, const cplx* __restrict__ G,
+                              const cplx* __restrict__ Gb, cplx* __restrict__ A) {
+  const i64 nn = (i64)N * N, n3 = nn * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3 * T) return;
+  const i64 k = e / n3;
+  const i64 r = e - k * n3;
+  const int i = (int)(r / nn);
+  const int lm = (int)(r - (i64)i * nn);
+  const int l = lm / N, m = lm - (lm / N) * N;
+  A[e] = cmul(G[k * nn + (i64)i * N + l], Gb[k * nn + lm]) * V[(i64)i * N + m];
+}
+
+// S_ij = 2 G_ij R_ji - sum_l V_jl B[k][i]_lj  (bubble R = V (V P)^T, Eq. 17;
+// exchange from B[k][i] = A[k][i] x G, Eq. 16).
+__global__ void k_sym_finish(int N, int T, const double* __restrict__ V, const cplx* __restrict__ G,
+                             const cplx* __restrict__ R, const cplx* __restrict__ B, cplx* __restrict__ S) {
+  const i64 nn = (i64)N * N;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn * T) return;
+  const i64 k = e / nn;
+  const int r = (int)(e - k * nn);
+  const int i = r / N, j = r - (r / N) * N;
+  const cplx* b = B + (k * N + i) * nn + j;
+  cplx x = mk(0.0, 0.0);
+  for (int l = 0; l < N; ++l) x += b[(i64)l * N] * V[(i64)j * N + l];
+  S[e] = cmul(G[e], R[k * nn + (i64)j * N + i]) * 2.0 - x;
+}
+
+// y = x + 0 i
+__global__ void k_real_to_c(i64 n, const double* __restrict__ x, cplx* __restrict__ y) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = mk(x[e], 0.0);
+}
+
 // x <- (a + i b) x
 __global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;

@@ -242,6 +242,48 @@ PropPlan prop_plan(int N, int n_end, int prec) {
   return p;
 }
 
+// Workspace of the special-vertex collision integrals: the GKBA history and
+// self-energy areas of coll_plan (no contraction chain), and for the symmetric
+// basis the float64 operands of the bubble and exchange products for a chunk
+// of past times (the exchange operand holds N^3 per slice).
+struct VertPlan {
+  size_t U, X, Y, Gl, Gg, Glb, Ggb, Sl, Sg, terms, ex1, ex2, Vc, P, Q, R, A, B, end;
+  int chunk;
+};
+VertPlan vert_plan(int N, int T, int vertex) {
+  VertPlan p;
+  const size_t m = al((size_t)N * N * C128), hist = al((size_t)T * N * N * C128);
+  size_t o = 0;
+  p.U = o; o += hist;
+  p.X = o; o += hist;
+  p.Y = o; o += hist;
+  p.Gl = o; o += hist;
+  p.Gg = o; o += hist;
+  p.Glb = o; o += hist;
+  p.Ggb = o; o += hist;
+  p.Sl = o; o += hist;
+  p.Sg = o; o += hist;
+  p.terms = o; o += hist;
+  p.ex1 = o; o += m;
+  p.ex2 = o; o += m;
+  p.chunk = 0;
+  p.Vc = p.P = p.Q = p.R = p.A = p.B = o;
+  if (vertex == SB2_VERTEX_SYMMETRIC) {
+    const size_t n3 = (size_t)N * N * N * C128;
+    long long ch = (long long)((size_t(1) << 29) / n3);
+    p.chunk = (int)(ch < 1 ? 1 : (ch > T ? T : ch));
+    p.Vc = o; o += m;
+    p.P = o; o += al((size_t)p.chunk * N * N * C128);
+    p.Q = o; o += al((size_t)p.chunk * N * N * C128);
+    p.R = o; o += al((size_t)p.chunk * N * N * C128);
+    p.A = o; o += al((size_t)p.chunk * n3);
+    p.B = o; o += al((size_t)p.chunk * n3);
+  }
+  p.end = o;
+  return p;
+}
+
+
 
 inline char* at(void* ws, size_t off) { return reinterpret_cast<char*>(ws) + off; }
 
@@ -1166,6 +1208,12 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
     case SB2_OP_PROPAGATE:
       if (T < 1 || T > SB2_MAX_T) return 0;
       return prop_plan(N, T, prec).end;
+    case SB2_OP_COLLISION_DIAGONAL:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return vert_plan(N, T, SB2_VERTEX_DIAGONAL).end;
+    case SB2_OP_COLLISION_SYMMETRIC:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return vert_plan(N, T, SB2_VERTEX_SYMMETRIC).end;
     default:
       return 0;
   }
@@ -1181,6 +1229,24 @@ int sb2_sigma(int N, int B, const double* v, const void* Gl, const void* Gg, voi
   hipError_t e = sigma_pairs(prec, N, B, v, Gl, Gg, nullptr, nullptr, 1, reinterpret_cast<cplx*>(Sl),
                              reinterpret_cast<cplx*>(Sg), nullptr, nullptr, p, ws, s);
   return e == hipSuccess ? SB2_OK : SB2_EHIP;
+}
+
+// I = dt sum_k [Sigma^>_k G^<(t_k,t) - Sigma^<_k G^>(t_k,t)] (Eq. 9), float64.
+hipError_t collision_terms(int N, int T, const cplx* Sl, const cplx* Sg, const cplx* Glb, const cplx* Ggb,
+                           cplx* terms, double dt, cplx* I_out, hipStream_t s) {
+  const i64 nn = (i64)N * N;
+  StageTimer tm(7, s);
+  GemmArgs g = gdef();
+  g.M = N; g.N = N; g.K = N;
+  g.A = Sg; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+  g.B = Glb; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+  g.C = terms; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+  hipError_t e;
+  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+  g.A = Sl; g.B = Ggb; g.alpha_re = -1.0; g.beta1 = 1;
+  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt, I_out);
+  return hipGetLastError();
 }
 
 // Collision integral from given propagators U[k] = U(t, t_k), k < T (Eq. 10
@@ -1222,19 +1288,7 @@ hipError_t collision_core(int N, int T, const double* v, const cplx* U, const vo
   cplx* Ol = Sigma_out;
   cplx* Og = Sigma_out ? Ol + (i64)T * nn : nullptr;
   if ((e = sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s)) != hipSuccess) return e;
-
-  // terms_k = Sigma^>_k G^<(t_k,t) - Sigma^<_k G^>(t_k,t)
-  StageTimer tm(7, s);
-  g = gdef();
-  g.M = N; g.N = N; g.K = N;
-  g.A = Sg; g.sAm = N; g.sAk = 1; g.sAbh = nn;
-  g.B = Glb; g.sBk = N; g.sBn = 1; g.sBbh = nn;
-  g.C = terms; g.sCm = N; g.sCn = 1; g.sCbh = nn;
-  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
-  g.A = Sl; g.B = Ggb; g.alpha_re = -1.0; g.beta1 = 1;
-  if ((e = zgemm(g, T, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt, I_out);
-  return hipGetLastError();
+  return collision_terms(N, T, Sl, Sg, Glb, Ggb, terms, dt, I_out, s);
 }
 
 int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, void* I_out,
@@ -1264,6 +1318,90 @@ int sb2_collision_prop(int N, int T, const double* v, const void* U_hist, const 
   SB2_TRY(collision_core(N, T, v, reinterpret_cast<const cplx*>(U_hist), rho_hist, dt,
                          reinterpret_cast<cplx*>(I_out), reinterpret_cast<cplx*>(Sigma_out), prec, c, ws,
                          reinterpret_cast<hipStream_t>(stream)));
+  return SB2_OK;
+}
+
+// Symmetric-basis self-energies of T slices (Eqs. 16-17), in chunks.
+hipError_t sigma_symmetric(int N, int T, const double* V, const cplx* G, const cplx* Gb, cplx* S,
+                           const VertPlan& p, void* ws, hipStream_t s) {
+  const i64 nn = (i64)N * N;
+  cplx* Vc = reinterpret_cast<cplx*>(at(ws, p.Vc));
+  cplx* P = reinterpret_cast<cplx*>(at(ws, p.P));
+  cplx* Q = reinterpret_cast<cplx*>(at(ws, p.Q));
+  cplx* R = reinterpret_cast<cplx*>(at(ws, p.R));
+  cplx* A = reinterpret_cast<cplx*>(at(ws, p.A));
+  cplx* B = reinterpret_cast<cplx*>(at(ws, p.B));
+  hipError_t e;
+  for (int c0 = 0; c0 < T; c0 += p.chunk) {
+    const int c = T - c0 < p.chunk ? T - c0 : p.chunk;
+    const cplx* Gc = G + (i64)c0 * nn;
+    const cplx* Gbc = Gb + (i64)c0 * nn;
+    hipLaunchKernelGGL(k_sym_bubble_in, dim3(blocks((long long)c * nn, 256)), dim3(256), 0, s, N, c, Gc, Gbc, P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GemmArgs g = gdef();                                  // Q = V P
+    g.M = N; g.N = N; g.K = N;
+    g.A = Vc; g.sAm = N; g.sAk = 1; g.sAbh = 0;
+    g.B = P; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+    g.C = Q; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, c, s)) != hipSuccess) return e;
+    g = gdef();                                           // R = V Q^T
+    g.M = N; g.N = N; g.K = N;
+    g.A = Vc; g.sAm = N; g.sAk = 1; g.sAbh = 0;
+    g.B = Q; g.sBk = 1; g.sBn = N; g.sBbh = nn;
+    g.C = R; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, c, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sym_exch_in, dim3(blocks((long long)c * nn * N, 256)), dim3(256), 0, s, N, c, V, Gc, Gbc,
+                       A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    g = gdef();                                           // B[k][i] = A[k][i] G[k]
+    g.M = N; g.N = N; g.K = N;
+    g.nbl = N;
+    g.A = A; g.sAm = N; g.sAk = 1; g.sAbh = nn * N; g.sAbl = nn;
+    g.B = Gc; g.sBk = N; g.sBn = 1; g.sBbh = nn; g.sBbl = 0;
+    g.C = B; g.sCm = N; g.sCn = 1; g.sCbh = nn * N; g.sCbl = nn;
+    if ((e = zgemm(g, c * N, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sym_finish, dim3(blocks((long long)c * nn, 256)), dim3(256), 0, s, N, c, V, Gc, R, B,
+                       S + (i64)c0 * nn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const void* h, const void* rho_hist,
+                         double dt, void* I_out, void* Sigma_out, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!vparam || !h || !rho_hist || !I_out || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  if (vertex != SB2_VERTEX_DIAGONAL && vertex != SB2_VERTEX_SYMMETRIC) return SB2_EINVAL;
+  const VertPlan p = vert_plan(N, T, vertex);
+  if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const i64 nn = (i64)N * N;
+  auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
+  SB2_TRY(gkba_history(N, T, h, rho_hist, dt, P(p.U), P(p.X), P(p.Y), P(p.Gl), P(p.Gg), P(p.Glb), P(p.Ggb),
+                       P(p.ex1), P(p.ex2), s));
+  {
+    StageTimer tm(6, s);
+    if (vertex == SB2_VERTEX_DIAGONAL) {
+      const dim3 grid(blocks((long long)T * nn, 256));
+      hipLaunchKernelGGL(k_sigma_diag, grid, dim3(256), 0, s, N, T, vparam, P(p.Gl), P(p.Ggb), P(p.Sl));
+      SB2_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_sigma_diag, grid, dim3(256), 0, s, N, T, vparam, P(p.Gg), P(p.Glb), P(p.Sg));
+      SB2_TRY(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(k_real_to_c, dim3(blocks(nn, 256)), dim3(256), 0, s, nn, vparam, P(p.Vc));
+      SB2_TRY(hipGetLastError());
+      SB2_TRY(sigma_symmetric(N, T, vparam, P(p.Gl), P(p.Ggb), P(p.Sl), p, ws, s));
+      SB2_TRY(sigma_symmetric(N, T, vparam, P(p.Gg), P(p.Glb), P(p.Sg), p, ws, s));
+    }
+  }
+  if (Sigma_out) {
+    const size_t bytes = (size_t)T * nn * C128;
+    SB2_TRY(hipMemcpyAsync(Sigma_out, P(p.Sl), bytes, hipMemcpyDeviceToDevice, s));
+    SB2_TRY(hipMemcpyAsync(reinterpret_cast<cplx*>(Sigma_out) + (i64)T * nn, P(p.Sg), bytes,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  SB2_TRY(collision_terms(N, T, P(p.Sl), P(p.Sg), P(p.Glb), P(p.Ggb), P(p.terms), dt,
+                          reinterpret_cast<cplx*>(I_out), s));
   return SB2_OK;
 }
 

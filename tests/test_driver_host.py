@@ -18,8 +18,8 @@ def L():
 
 def test_new_functions_are_declared_and_exported(L):
     names = set(_lib.header_functions())
-    assert {"sb2_collision_prop", "sb2_gkba_propagate"} <= names
-    for n in ("sb2_collision_prop", "sb2_gkba_propagate"):
+    assert {"sb2_collision_prop", "sb2_gkba_propagate", "sb2_collision_vertex"} <= names
+    for n in ("sb2_collision_prop", "sb2_gkba_propagate", "sb2_collision_vertex"):
         assert hasattr(L, n)
 
 
@@ -95,3 +95,17 @@ def test_checkpoint_rejects_inconsistent_states(tmp_path):
     st["dt"] = -1.0
     with pytest.raises(ValueError):
         driver.check_state(st)
+
+
+def test_vertex_argument_errors_and_workspace(L):
+    c = L.sb2_collision_vertex
+    assert c(0, 4, 1, FAKE, FAKE, FAKE, 0.05, FAKE, None, FAKE, BIG, None) == -2
+    assert c(8, 0, 1, FAKE, FAKE, FAKE, 0.05, FAKE, None, FAKE, BIG, None) == -2
+    assert c(8, 4, 3, FAKE, FAKE, FAKE, 0.05, FAKE, None, FAKE, BIG, None) == -1
+    assert c(8, 4, 2, None, FAKE, FAKE, 0.05, FAKE, None, FAKE, BIG, None) == -1
+    assert c(8, 4, 1, FAKE, FAKE, FAKE, -1.0, FAKE, None, FAKE, BIG, None) == -1
+    assert c(8, 4, 2, FAKE, FAKE, FAKE, 0.05, FAKE, None, FAKE, 64, None) == -3
+    ws = _lib.sb2_workspace_size
+    assert 0 < ws("collision_diagonal", 10, 5) < ws("collision_symmetric", 10, 5)
+    # the symmetric-basis exchange operands are bounded by chunking (about 1 GiB)
+    assert ws("collision_symmetric", 128, 2000) - ws("collision_diagonal", 128, 2000) < (1 << 31)

@@ -1,0 +1,115 @@
+"""GPU parity of the special-vertex collision integrals (Sec. III A, III B)
+against the FP64 oracle: the diagonal (Hubbard-like) and the symmetric
+(density-density) basis, including the chain parameters of the paper's
+examples and a symmetric-basis case whose exchange runs in several chunks."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sb2_oracle as o
+from paper_1905_01180_amd import _lib
+from paper_1905_01180_amd import inputs as gen
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def relf(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def err_i(got, ref, sig, h, rho, dt):
+    """|I - I_ref| relative to the size of the summed terms dt sum_k
+    (|Sigma^>_k| |Gbar^<_k| + |Sigma^<_k| |Gbar^>_k|): I itself can cancel to
+    rounding noise (exactly for N = 1)."""
+    _, _, _, glb, ggb = o.gkba_history(h, rho, dt)
+    scale = dt * sum(np.linalg.norm(sig[k][1]) * np.linalg.norm(glb[k]) + np.linalg.norm(sig[k][0]) *
+                     np.linalg.norm(ggb[k]) for k in range(rho.shape[0]))
+    return np.linalg.norm(np.asarray(got) - np.asarray(ref)) / max(scale, 1e-300)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _params(n, seed):
+    g = gen.rng(80, seed, 0)
+    u = g.uniform(0.2, 1.0, n)
+    vm = g.uniform(0.05, 0.6, (n, n))
+    return u, 0.5 * (vm + vm.T)
+
+
+@pytest.mark.parametrize("n,t", [(1, 3), (7, 1), (7, 5), (33, 12)])
+def test_diagonal_basis(n, t):
+    s = gen.make_system(n, t, config_id=81)
+    u, _ = _params(n, n)
+    ref, sig = o.collision_with(lambda g_, b_: o.sigma_diagonal_basis(u, g_, b_), s.h, s.rho_hist, s.dt,
+                                return_sigma=True)
+    got, gs = _lib.sb2_collision_vertex("diagonal", _dev(u), _dev(s.h), _dev(s.rho_hist), s.dt, return_sigma=True)
+    got, gs = got.cpu().numpy(), gs.cpu().numpy()
+    e = err_i(got, ref, sig, s.h, s.rho_hist, s.dt)
+    print(f"diagonal N={n} T={t}: I err {e:.2e}", flush=True)
+    assert e < 1e-13
+    for k in range(t):
+        assert relf(gs[0, k], sig[k][0]) < 1e-12
+        assert relf(gs[1, k], sig[k][1]) < 1e-12
+
+
+@pytest.mark.parametrize("n,t", [(2, 3), (10, 4), (24, 3)])
+def test_symmetric_basis(n, t):
+    s = gen.make_system(n, t, config_id=82)
+    _, vm = _params(n, n)
+    ref, sig = o.collision_with(lambda g_, b_: o.sigma_symmetric_basis_vec(vm, g_, b_), s.h, s.rho_hist, s.dt,
+                                return_sigma=True)
+    got, gs = _lib.sb2_collision_vertex("symmetric", _dev(vm), _dev(s.h), _dev(s.rho_hist), s.dt,
+                                        return_sigma=True)
+    got, gs = got.cpu().numpy(), gs.cpu().numpy()
+    e = err_i(got, ref, sig, s.h, s.rho_hist, s.dt)
+    print(f"symmetric N={n} T={t}: I err {e:.2e}", flush=True)
+    assert e < 1e-13
+    for k in range(t):
+        assert relf(gs[0, k], sig[k][0]) < 1e-12
+        assert relf(gs[1, k], sig[k][1]) < 1e-12
+
+
+def test_symmetric_basis_in_chunks():
+    # N = 128: 16 past times per exchange chunk, T = 17 -> two chunks; sampled
+    # self-energies at both sides of the chunk boundary against the oracle, I
+    # against the general path with the materialised vertex
+    n, t = 128, 17
+    s = gen.make_system(n, t, config_id=83)
+    _, vm = _params(n, 5)
+    i_v, gs = _lib.sb2_collision_vertex("symmetric", _dev(vm), _dev(s.h), _dev(s.rho_hist), s.dt,
+                                        return_sigma=True)
+    gs = gs.cpu().numpy()
+    _, gl, gg, glb, ggb = o.gkba_history(s.h, s.rho_hist, s.dt)
+    for k in (0, 15, 16):
+        assert relf(gs[0, k], o.sigma_symmetric_basis_vec(vm, gl[k], ggb[k])) < 1e-12
+        assert relf(gs[1, k], o.sigma_symmetric_basis_vec(vm, gg[k], glb[k])) < 1e-12
+    i_g = _lib.sb2_collision(_dev(o.vertex_symmetric(vm)), _dev(s.h), _dev(s.rho_hist), s.dt, "fp64")
+    assert relf(i_v.cpu().numpy(), i_g.cpu().numpy()) < 1e-11
+
+
+def test_paper_chain_parameters():
+    # N_b = 10 chains of Sec. IV: hopping J = -1 between neighbours, U = 1,
+    # V_ij = U / sqrt(1 + |i - j|^2); the special-vertex paths equal the general
+    # path with the materialised vertex and the oracle
+    n, t, dt = 10, 20, 0.05
+    hop = np.zeros((n, n), np.complex128)
+    for i in range(n - 1):
+        hop[i, i + 1] = hop[i + 1, i] = -1.0
+    idx = np.arange(n)
+    vm = 1.0 / np.sqrt(1.0 + (idx[:, None] - idx[None, :]) ** 2.0)
+    u = np.ones(n)
+    rho = gen.rho_history(n, t, dt, gen.rng(84, 0, 0))
+    for vertex, param, tensor, fn in (
+            ("diagonal", u, o.vertex_diagonal(u), lambda g_, b_: o.sigma_diagonal_basis(u, g_, b_)),
+            ("symmetric", vm, o.vertex_symmetric(vm), lambda g_, b_: o.sigma_symmetric_basis_vec(vm, g_, b_))):
+        ref = o.collision_with(fn, hop, rho, dt)
+        got = _lib.sb2_collision_vertex(vertex, _dev(param), _dev(hop), _dev(rho), dt).cpu().numpy()
+        gen_path = _lib.sb2_collision(_dev(tensor), _dev(hop), _dev(rho), dt, "fp64").cpu().numpy()
+        print(f"chain {vertex}: vs oracle {relf(got, ref):.2e}, vs general path {relf(got, gen_path):.2e}",
+              flush=True)
+        assert relf(got, ref) < 1e-12
+        assert relf(got, gen_path) < 1e-12
