@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run sb2_autotune for the workload before timing")
     ap.add_argument("--propagate", action="store_true",
                     help="time whole GKBA propagation steps (HF + second-Born collisions) from a history of --t steps")
+    ap.add_argument("--vertex", choices=["diagonal", "symmetric"],
+                    help="time the special-vertex collision integral (float64) at --n, --t")
     ap.add_argument("--small-batch", action="store_true",
                     help="with --batched: 32 small systems (N 8..24, T 16..64) instead of N 24..96, T 64..512")
     args = ap.parse_args()
@@ -124,6 +126,8 @@ def main():
         return batched(args, torch, _lib, gen, dev)
     if args.propagate:
         return propagate(args, torch, _lib, gen, dev)
+    if args.vertex:
+        return vertex(args, torch, _lib, gen, dev)
 
     cid = 2 if (args.n, args.t) == (100, 1000) else 99
     log(f"generating inputs N={args.n} T={args.t}")
@@ -340,6 +344,64 @@ def batched(args, torch, _lib, gen, dev):
         "tflops_algorithmic": flops / t_grp_g / 1e12,
         "grouped_vs_single_max_rel_diff": dev_max, "graph_replay_bitwise_equal": replay_equal,
         "stage_ms_and_launches": prof,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def vertex(args, torch, _lib, gen, dev):
+    """Collision integral for a special vertex (Sec. III A / III B), float64:
+    the GKBA functions and the sum over past times as in the general path, the
+    self-energy by Eq. 14 (diagonal) or Eqs. 16-17 (symmetric).  value = I(t)
+    evaluations per second.  The roofline entry covers the self-energy stage:
+    for the symmetric basis its exchange and bubble products (16 T N^4 +
+    32 T N^3 flops) against the FP64 matrix-core peak."""
+    import ctypes
+    import numpy as np
+    n, t = args.n, args.t
+    cid = 2 if (n, t) == (100, 1000) else 99
+    log(f"vertex {args.vertex}: N={n} T={t}")
+    s = gen.make_system(n, t, config_id=cid)
+    g = gen.rng(cid, 0, 9)
+    if args.vertex == "diagonal":
+        param = torch.from_numpy(g.uniform(0.2, 1.0, n)).to(dev)
+    else:
+        idx = np.arange(n)
+        param = torch.from_numpy(0.5 / np.sqrt(1.0 + (idx[:, None] - idx[None, :]) ** 2.0)).to(dev)
+    h = torch.from_numpy(s.h).to(dev)
+    rho = torch.from_numpy(s.rho_hist).to(dev)
+    run = lambda: _lib.sb2_collision_vertex(args.vertex, param, h, rho, s.dt)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    L = _lib.lib()
+    L.sb2_profile_enable(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    ms = (ctypes.c_double * 8)()
+    cnt = (ctypes.c_int * 8)()
+    st = L.sb2_profile_read(ms, cnt, 8)
+    L.sb2_profile_enable(0)
+    stages = {"gkba": ms[5] / args.steps, "sigma": ms[6] / args.steps, "collision": ms[7] / args.steps} \
+        if st == 0 else None
+    n3, n4 = float(n) ** 3, float(n) ** 4
+    common = 40.0 * t * n3                     # propagators, X/Y, collision terms (complex MAC = 8 flops)
+    sig_flops = 16.0 * t * n4 + 32.0 * t * n3 if args.vertex == "symmetric" else 2.0 * t * n * n * 8.0
+    roof = None
+    if stages and args.vertex == "symmetric":
+        ach = sig_flops / (stages["sigma"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None, "kernel": "self-energy stage (sym. basis)"}
+    out = {
+        "metric": "special-vertex GKBA collision integral steps/s (N=%d, T=%d, %s basis)" % (n, t, args.vertex),
+        "value": 1.0 / sec, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "GKBA collision integral, %s-basis vertex, N=%d, T=%d, dt=%g" % (args.vertex, n, t, s.dt),
+                   "N": n, "T": t},
+        "tflops_algorithmic": (common + sig_flops) / sec / 1e12, "roofline": roof, "stage_ms": stages,
     }
     print(json.dumps(out), flush=True)
 

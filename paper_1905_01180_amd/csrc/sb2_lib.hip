@@ -1353,13 +1353,12 @@ hipError_t sigma_symmetric(int N, int T, const double* V, const cplx* G, const c
     hipLaunchKernelGGL(k_sym_exch_in, dim3(blocks((long long)c * nn * N, 256)), dim3(256), 0, s, N, c, V, Gc, Gbc,
                        A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    g = gdef();                                           // B[k][i] = A[k][i] G[k]
-    g.M = N; g.N = N; g.K = N;
-    g.nbl = N;
-    g.A = A; g.sAm = N; g.sAk = 1; g.sAbh = nn * N; g.sAbl = nn;
-    g.B = Gc; g.sBk = N; g.sBn = 1; g.sBbh = nn; g.sBbl = 0;
-    g.C = B; g.sCm = N; g.sCn = 1; g.sCbh = nn * N; g.sCbl = nn;
-    if ((e = zgemm(g, c * N, s)) != hipSuccess) return e;
+    g = gdef();                                           // B[k][i] = A[k][i] G[k]: one (N^2 x N) x (N x N)
+    g.M = N * N; g.N = N; g.K = N;                        // product per past time, rows (i, l)
+    g.A = A; g.sAm = N; g.sAk = 1; g.sAbh = nn * N;
+    g.B = Gc; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+    g.C = B; g.sCm = N; g.sCn = 1; g.sCbh = nn * N;
+    if ((e = zgemm(g, c, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sym_finish, dim3(blocks((long long)c * nn, 256)), dim3(256), 0, s, N, c, V, Gc, R, B,
                        S + (i64)c0 * nn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
