@@ -157,6 +157,21 @@ typedef enum {
 int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const void* h, const void* rho_hist,
                          double dt, void* I_out, void* Sigma_out, void* ws, size_t ws_bytes, void* stream);
 
+/* 8-fold packed interaction tensor.  For real basis functions the Coulomb
+ * integrals of Eq. 3 obey the 8-point symmetry of Eq. 6: v_ijkl depends only
+ * on the unordered pairs {i, l} (both orbitals at r) and {j, k} (at r') and
+ * is unchanged when the two pairs are exchanged.  Packed storage keeps one
+ * float64 per orbit:
+ *   pair(a, b) = max(a,b) (max(a,b) + 1) / 2 + min(a,b)
+ *   packed[pair(pair(i, l), pair(j, k))] = v_ijkl
+ * sb2_v8_count: number of packed values, P (P + 1) / 2 with P = N (N + 1) / 2
+ * (about N^4 / 8); 0 for N out of range.
+ * sb2_v8_expand: write the full N^4 tensor v (row-major v[i][j][k][l], as the
+ * other entry points take it) from the packed values; device pointers,
+ * enqueued on stream.  Errors: SB2_ESHAPE, SB2_EINVAL (null pointer).       */
+size_t sb2_v8_count(int N);
+int sb2_v8_expand(int N, const double* packed, double* v, void* stream);
+
 /* Terms of the equation of motion included by sb2_gkba_propagate. */
 typedef enum {
   SB2_PROP_HF = 1,         /* Sigma_HF (Eq. 12) in the propagator and the commutator */

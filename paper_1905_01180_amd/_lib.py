@@ -76,6 +76,10 @@ def lib() -> ctypes.CDLL:
         L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
         L.sb2_collision_prop.restype = _i
         L.sb2_collision_prop.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
+        L.sb2_v8_count.restype = _sz
+        L.sb2_v8_count.argtypes = [_i]
+        L.sb2_v8_expand.restype = _i
+        L.sb2_v8_expand.argtypes = [_i, _vp, _vp, _vp]
         L.sb2_collision_vertex.restype = _i
         L.sb2_collision_vertex.argtypes = [_i, _i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _sz, _vp]
         L.sb2_gkba_propagate.restype = _i
@@ -188,6 +192,14 @@ def sb2_collision_prop(v: torch.Tensor, u_hist: torch.Tensor, rho_hist: torch.Te
           out.data_ptr(), sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(),
           _stream(v.device))
     return (out, sig) if return_sigma else out
+
+
+def sb2_v8_expand(packed: torch.Tensor, n: int) -> torch.Tensor:
+    """Full (N, N, N, N) float64 tensor from its 8-fold packed values (device)."""
+    _check(packed, "packed", torch.float64, (int(lib().sb2_v8_count(n)),))
+    v = torch.empty((n, n, n, n), dtype=torch.float64, device=packed.device)
+    _call("sb2_v8_expand", n, packed.data_ptr(), v.data_ptr(), _stream(packed.device))
+    return v
 
 
 def sb2_collision_vertex(vertex: str, param: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: float,

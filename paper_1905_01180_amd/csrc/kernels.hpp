@@ -553,6 +553,30 @@ __global__ void k_real_to_c(i64 n, const double* __restrict__ x, cplx* __restric
   if (e < n) y[e] = mk(x[e], 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// 8-fold packed interaction tensor (real orbitals, Eq. 6): v_ijkl depends only
+// on the unordered pairs {i, l} (the orbitals at r) and {j, k} (at r') and on
+// their order, so it is stored once per unordered pair of unordered pairs:
+//   pair(a, b) = max(a,b) (max(a,b) + 1) / 2 + min(a,b),
+//   packed[ tri(P, Q) ],  P = pair(i, l), Q = pair(j, k),
+//   tri(P, Q) = max(P,Q) (max(P,Q) + 1) / 2 + min(P,Q).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ i64 v8_tri(i64 a, i64 b) {
+  const i64 hi = a > b ? a : b, lo = a > b ? b : a;
+  return hi * (hi + 1) / 2 + lo;
+}
+
+// v[i][j][k][l] = packed[tri(pair(i, l), pair(j, k))] for all N^4 entries.
+__global__ void k_v8_expand(int N, const double* __restrict__ packed, double* __restrict__ v) {
+  const i64 nn = (i64)N * N, total = nn * nn;
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const i64 ij = e / nn, kl = e - ij * nn;         // e = (i N + j) N^2 + (k N + l)
+  const int i = (int)(ij / N), j = (int)(ij - (ij / N) * N);
+  const int k = (int)(kl / N), l = (int)(kl - (kl / N) * N);
+  v[e] = packed[v8_tri(v8_tri(i, l), v8_tri(j, k))];
+}
+
 // x <- (a + i b) x
 __global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;

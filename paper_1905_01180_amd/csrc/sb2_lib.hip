@@ -1404,6 +1404,22 @@ int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const v
   return SB2_OK;
 }
 
+size_t sb2_v8_count(int N) {
+  if (N < 1 || N > SB2_MAX_N) return 0;
+  const size_t np = (size_t)N * (N + 1) / 2;
+  return np * (np + 1) / 2;
+}
+
+int sb2_v8_expand(int N, const double* packed, double* v, void* stream) {
+  if (N < 1 || N > SB2_MAX_N) return SB2_ESHAPE;
+  if (!packed || !v) return SB2_EINVAL;
+  const long long total = (long long)N * N * N * N;
+  hipLaunchKernelGGL(k_v8_expand, dim3(blocks(total, 256)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), N,
+                     packed, v);
+  SB2_TRY(hipGetLastError());
+  return SB2_OK;
+}
+
 int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
                        void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;

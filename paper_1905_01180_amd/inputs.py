@@ -72,6 +72,21 @@ def interaction_generic(n: int, g: np.random.Generator, vmax: float = 0.5) -> np
     return np.ascontiguousarray(v)
 
 
+def interaction_real_orbitals(n: int, g: np.random.Generator, m: int = 0, vmax: float = 0.5) -> np.ndarray:
+    """Real v_ijkl = sum_{r,r'} phi_i(r) phi_j(r') K(r,r') phi_k(r') phi_l(r) from n
+    orthonormal real functions on m grid points and K(r,r') = 1/sqrt(1+(x-x')^2):
+    the full 8-point symmetry of real orbitals; max|v| = vmax."""
+    m = m or 2 * n + 8
+    phi, _ = np.linalg.qr(g.standard_normal((m, n)))
+    x = np.linspace(-3.0, 3.0, m)
+    kern = 1.0 / np.sqrt(1.0 + (x[:, None] - x[None, :]) ** 2)
+    f = (phi[:, :, None] * phi[:, None, :]).reshape(m, n * n)       # f[r, (a,b)] = phi_a(r) phi_b(r)
+    x_ab_cd = f.T @ kern @ f                                         # [(i,l), (j,k)]
+    v = x_ab_cd.reshape(n, n, n, n).transpose(0, 2, 3, 1)            # (i,l,j,k) -> (i,j,k,l)
+    v *= vmax / np.abs(v).max()
+    return np.ascontiguousarray(v)
+
+
 def haar_unitary(n: int, g: np.random.Generator) -> np.ndarray:
     z = (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))) / np.sqrt(2.0)
     q, r = np.linalg.qr(z)
