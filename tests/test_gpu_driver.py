@@ -127,3 +127,39 @@ def test_zero_interaction_is_free_propagation():
         u = o.propagator(h, m * DT)
         assert relf(st["rho"][m], u @ rho0 @ u.conj().T) < 1e-12
     assert np.abs(st["i"]).max() == 0.0
+
+
+def test_propagation_graph_replay_matches_eager():
+    # the whole multi-step propagation is one enqueue without host synchronisation:
+    # capture it, restore the state before every replay, compare bit for bit
+    n, n0, k = 10, 3, 4
+    h, v, rho0 = _system(n, 21)
+    st = d.propagate(v, h, DT, n0, d.new_state(rho0))
+    cap = n0 + k
+    vd, hd = _dev(v), _dev(h)
+    rho = torch.zeros((cap + 1, n, n), dtype=torch.complex128, device=DEV)
+    u = torch.zeros((cap, n, n), dtype=torch.complex128, device=DEV)
+    ih = torch.zeros((cap, n, n), dtype=torch.complex128, device=DEV)
+    rho[: n0 + 1].copy_(_dev(st["rho"]))
+    u[:n0].copy_(_dev(st["u"]))
+    rho_init, u_init = rho.clone(), u.clone()
+    print("case: propagation graph replay", flush=True)
+    _lib.sb2_gkba_propagate(vd, hd, rho, u, n0, k, DT, "fp16x3", i_hist=ih)
+    torch.cuda.synchronize()
+    eager = (rho.clone(), u.clone(), ih.clone())
+    rho.copy_(rho_init)
+    u.copy_(u_init)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        _lib.sb2_gkba_propagate(vd, hd, rho, u, n0, k, DT, "fp16x3", i_hist=ih)
+    for rep in range(3):
+        rho.copy_(rho_init)
+        u.copy_(u_init)
+        ih.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((rho, u, ih), eager):
+            assert torch.equal(a, b), rep
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between replays

@@ -113,3 +113,24 @@ def test_paper_chain_parameters():
               flush=True)
         assert relf(got, ref) < 1e-12
         assert relf(got, gen_path) < 1e-12
+
+
+@pytest.mark.parametrize("vertex", ["diagonal", "symmetric"])
+def test_vertex_graph_replay_matches_eager(vertex):
+    n, t = 20, 6
+    s = gen.make_system(n, t, config_id=85)
+    u, vm = _params(n, 7)
+    param, h, rho = _dev(u if vertex == "diagonal" else vm), _dev(s.h), _dev(s.rho_hist)
+    print(f"case: {vertex} graph replay", flush=True)
+    eager = _lib.sb2_collision_vertex(vertex, param, h, rho, s.dt).clone()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = _lib.sb2_collision_vertex(vertex, param, h, rho, s.dt)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()
