@@ -12,6 +12,10 @@
 namespace sb2 {
 
 enum ScaleWord { S_GMAX = 0, S_GBMAX, S_WMAX, S_VMAX, S_AMAX, S_BMAX, S_CMAX, S_NWORDS };
+// After the scale words: a 1 KiB sink (16 bytes per lane of a wave) that
+// takes the stores of out-of-range tile elements, so that a tile's stores are
+// issued unconditionally (a fixed number per wave).
+constexpr int S_TRASH = 64, S_TRASH_WORDS = 256;
 
 // Everything a chain stage needs to know about one system's current chunk.
 struct ChainRefs {
@@ -47,6 +51,7 @@ __host__ __device__ inline StreamArgs stage_args(int stage, const ChainRefs& r, 
   const i64 n = r.N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
   const bool h16 = r.prec == 2;
   StreamArgs g = sargs_zero();
+  g.trash = r.scal + S_TRASH;
   void* Cc = r.C3 ? r.C3 : r.X1;
   nbatch = 1;
   if (stage == 0) {

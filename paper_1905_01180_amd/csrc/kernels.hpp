@@ -365,18 +365,21 @@ __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* _
     tile[q][jj][mm] = w;
   }
   __syncthreads();
-  // write rows x = (j, s, q), elements m0..m0+7
+  // write rows x = (j, s, q), elements m0..m0+7; the row padding m = N .. KpW-1
+  // is written as zeros (readers may load whole 8-element groups)
   for (int L = threadIdx.x; L < 16 * N * 8; L += blockDim.x) {
     const int mm = L & 7, jq = L >> 3;
     const int jj = jq / N, q = jq - (jq / N) * N;
     const int m = m0 + mm, j = j0 + jj;
-    if (m < N && j < N) {
+    if (m < KpW && j < N) {
       const i64 x = ((i64)j * N + s) * N + q;
-      double val;
-      if constexpr (sizeof(T) == 8) {
-        val = 2.0 * v[((i64)m * N + q) * nn + (i64)s * N + j] - v[((i64)q * N + m) * nn + (i64)s * N + j];
-      } else {
-        val = tile[q][jj][mm];
+      double val = 0.0;
+      if (m < N) {
+        if constexpr (sizeof(T) == 8) {
+          val = 2.0 * v[((i64)m * N + q) * nn + (i64)s * N + j] - v[((i64)q * N + m) * nn + (i64)s * N + j];
+        } else {
+          val = tile[q][jj][mm];
+        }
       }
       put_val<T>(W, plane, x * KpW + m, val, sc);
     }

@@ -168,7 +168,7 @@ ChainPlan chain_plan(int N, int pairs, int prec, size_t base, int forceS = 0, do
   }
   const size_t ib = inter_bytes(prec);
   size_t o = base;
-  p.scal = o; o += al(S_NWORDS * 4);
+  p.scal = o; o += al((S_TRASH + S_TRASH_WORDS) * 4);
   p.w = o; o += al(n3 * (size_t)p.KpW * ib);
   p.vp = o; o += al((size_t)N * (size_t)vrow * ib);
   p.gs = o; o += al(2 * S * n2 * 2 * bb);

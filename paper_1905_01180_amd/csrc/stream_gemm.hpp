@@ -55,7 +55,18 @@ struct StreamArgs {
   const unsigned* smax;    // H16: scale sources (max |x| as float bits)
   const unsigned* xmax;
   unsigned* cmax;          // H16 producers: raised to max |out|
+  void* trash;             // >= 64 x 16 bytes: sink of out-of-range tile stores (stream1_body)
 };
+
+// The pointer unchanged, but opaque to the optimiser (an empty asm statement
+// on its value): a store through a selected address stays one unconditional
+// store instead of being split into branches.
+template <typename P>
+__device__ __forceinline__ __attribute__((address_space(1))) P* opaque(P* p) {
+  unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  asm volatile("" : "+v"(a));
+  return reinterpret_cast<__attribute__((address_space(1))) P*>(a);   // global memory
+}
 
 template <typename V, int N_>
 __device__ __forceinline__ void zero_arr(V (&a)[N_]) {
@@ -622,27 +633,15 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
       if (kg0 >= kend) continue;                            // uniform: whole group past K
       const int k = kg0 + KV * grp;
       if constexpr (H && !XC) {
+        // Whole 8-element groups at clamped addresses, never masked, so the
+        // loads stay in flight until the products use them: the row pitch
+        // sXx is a multiple of 8 with zero padding past K, the shared operand
+        // is zero for k >= K (so any finite value there contributes nothing),
+        // and rows past the end read the last row (their outputs are not stored).
         const _Float16* p = reinterpret_cast<const _Float16*>(Xb) + xbatch + (i64)xc * g.sXx;
-        hx8 vh, vl;
-        if (kg0 + KG <= kend) {
-          vh = *reinterpret_cast<const hx8*>(p + k);
-          vl = *reinterpret_cast<const hx8*>(p + g.sXplane + k);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int kk = min(k + e, kend - 1);
-            const bool ok = k + e < kend;
-            const _Float16 a = p[kk], b = p[g.sXplane + kk];
-            vh[e] = ok ? a : (_Float16)0.f;
-            vl[e] = ok ? b : (_Float16)0.f;
-          }
-        }
-        if (edge && !xv) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) { vh[e] = (_Float16)0.f; vl[e] = (_Float16)0.f; }
-        }
-        t.ph[q] = vh;
-        t.pl[q] = vl;
+        const int kc = min(k, (int)g.sXx - 8);
+        t.ph[q] = *reinterpret_cast<const hx8*>(p + kc);
+        t.pl[q] = *reinterpret_cast<const hx8*>(p + g.sXplane + kc);
       } else {
         const T* p = reinterpret_cast<const T*>(Xb) + XE * (xbatch + (i64)xc * g.sXx);
         if (kg0 + KG <= kend) {
@@ -765,6 +764,8 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
     const T usc = (T)unscale;                                // a power of two: exact
     // interior tiles (every row and column in range) store without per-element tests
     const bool interior = (x0 + 16 <= xlim) && (s0 + SR <= slim);
+    typedef OutT o2 __attribute__((ext_vector_type(2)));
+    o2* sink = reinterpret_cast<o2*>(g.trash) + lane;
     if constexpr (SA) {
       const int n = x0 + lr;
       const i64 coff = (i64)n * g.sCn;
@@ -774,14 +775,14 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int m = s0 + i * 16 + frag_row<T>(grp, q);
-          if (interior || (nv && m < g.M)) {
-            typedef OutT o2 __attribute__((ext_vector_type(2)));
-            o2 v;
-            v[0] = (OutT)(cr[i][q] * usc);
-            v[1] = (OutT)(ci[i][q] * usc);
-            *reinterpret_cast<o2*>(Cb + 2 * (fixoff[q] + i * fixstep + coff)) = v;
-            if constexpr (H) mx = fmaxf(mx, fmaxf(fabsf((float)v[0]), fabsf((float)v[1])));
-          }
+          const bool ok = interior || (nv && m < g.M);
+          o2 v;
+          v[0] = (OutT)(cr[i][q] * usc);
+          v[1] = (OutT)(ci[i][q] * usc);
+          // every element is stored (out-of-range ones into the sink): a fixed
+          // number of store instructions per tile
+          *opaque(ok ? reinterpret_cast<o2*>(Cb + 2 * (fixoff[q] + i * fixstep + coff)) : sink) = v;
+          if constexpr (H) mx = fmaxf(mx, ok ? fmaxf(fabsf((float)v[0]), fabsf((float)v[1])) : 0.f);
         }
       }
     } else {
@@ -803,31 +804,42 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
         const int n = s0 + i * 16 + lr;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if (interior || (rv[q] && n < g.N)) {
-            typedef OutT o2 __attribute__((ext_vector_type(2)));
-            o2 v;
-            v[0] = (OutT)(cr[i][q] * usc);
-            v[1] = (OutT)(ci[i][q] * usc);
-            *reinterpret_cast<o2*>(Cb + 2 * (roff[q] + fixoff[0] + i * fixstep)) = v;
-            if constexpr (H) mx = fmaxf(mx, fmaxf(fabsf((float)v[0]), fabsf((float)v[1])));
-          }
+          const bool ok = interior || (rv[q] && n < g.N);
+          o2 v;
+          v[0] = (OutT)(cr[i][q] * usc);
+          v[1] = (OutT)(ci[i][q] * usc);
+          *opaque(ok ? reinterpret_cast<o2*>(Cb + 2 * (roff[q] + fixoff[0] + i * fixstep)) : sink) = v;
+          if constexpr (H) mx = fmaxf(mx, ok ? fmaxf(fabsf((float)v[0]), fabsf((float)v[1])) : 0.f);
         }
       }
     }
   };
 
-  // super-group 0 of a tile lives in ta, super-group 1 in tb; each load is
-  // issued one super-group ahead of its use
+  // super-group 0 of a tile lives in ta, super-group 1 in tb; both loads of
+  // the next tile are issued before this tile's stores (the memory counter
+  // completes in order, so a load issued after the stores could only be
+  // waited for together with them)
   XT_ ta, tb;
   int tx = pp;
-  if (tx < tiles_x) load_sg(tx, 0, ta);
+  if (tx < tiles_x) {
+    load_sg(tx, 0, ta);
+    load_sg(tx, 1, tb);
+    // as many sink stores as one tile's epilogue: the loop is entered with the
+    // same memory-operation sequence as from its back edge
+    typedef OutT o2 __attribute__((ext_vector_type(2)));
+    o2 z;
+    z[0] = z[1] = (OutT)0;
+#pragma unroll
+    for (int e = 0; e < FS * 4; ++e) *opaque(reinterpret_cast<o2*>(g.trash) + lane) = z;
+  }
   for (; tx < tiles_x; tx += npersist) {
     zero_arr(cr);
     zero_arr(ci);
-    load_sg(tx, 1, tb);
+    const bool more = tx + npersist < tiles_x;
     compute_sg(0, ta);
-    if (tx + npersist < tiles_x) load_sg(tx + npersist, 0, ta);
+    if (more) load_sg(tx + npersist, 0, ta);
     compute_sg(1, tb);
+    if (more) load_sg(tx + npersist, 1, tb);
     epilogue(tx);
   }
   if constexpr (H) {
