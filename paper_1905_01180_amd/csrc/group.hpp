@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(512) k_r4_group(const ChainRefs* __restrict__ 
   const R4Args a = r4_args(refs[t.idx[i]]);
   const int tiles = r4_tiles(a);
   const int local = (int)(b - t.off[i]);
-  r4_body<FS>(a, local % tiles, local / tiles);
+  r4_body<FS, false>(a, local % tiles, local / tiles);   // 8-byte pair loads: any chunk length
 }
 
 }  // namespace sb2

@@ -40,8 +40,9 @@ struct R4Args {
   const unsigned* xmax;
 };
 
-// Workgroup (bx, by): columns 64 bx .., chunk by.
-template <int FS>
+// Workgroup (bx, by): columns 64 bx .., chunk by.  EVEN: the chunk length
+// kc is even (complex pairs of C are 16-byte aligned).
+template <int FS, bool EVEN>
 __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
   constexpr int NTH = 512, NCOL = 64, KS = 64, NKG = KS / 32;
   constexpr int FSP = (FS + 1) / 2 * 2, FH = FSP / 2;   // padded row fragments, per row half
@@ -99,7 +100,6 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
   // ---- C items: load e of lane l covers column 8 w + 2 e + l/32, complex
   // k = 2 (l%32), 2 (l%32) + 1 of the slab ----
   const int ck = 2 * (lane & 31), chalf = lane >> 5;
-  const bool even = (K & 1) == 0;                        // 16-byte aligned pairs (K >= 2 then)
   // columns past ncol read column ncol - 1 (discarded output columns)
   auto load_c = [&](int s, float4 (&dst)[PC]) {
     const int k = k0 + s * KS + ck;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
     for (int e = 0; e < PC; ++e) {
       const int c = min(col0 + 8 * w + 2 * e + chalf, a.ncol - 1);
       const float* p = Xz + 2 * ((i64)c * K);
-      if (even) {
+      if constexpr (EVEN) {
         dst[e] = *reinterpret_cast<const float4*>(p + 2 * min(k, K - 2));
       } else {
         const float2 x0 = *reinterpret_cast<const float2*>(p + 2 * min(k, K - 1));
@@ -181,16 +181,17 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
       }
   };
 
-  // two register sets: slab s + 2 is in flight while slab s is multiplied
+  // two register sets: slab s + 2 is in flight while slab s is multiplied.
+  // Loads are issued unconditionally (slabs past the end read clamped,
+  // in-bounds addresses and are never multiplied), so every iteration issues
+  // the same memory operations and each wait covers only the set it needs.
   hx8 va[PV], vb[PV];
   float4 ca[PC], cb[PC];
   if (nslab > 0) {
     load_v(0, va);
     load_c(0, ca);
-    if (nslab > 1) {
-      load_v(1, vb);
-      load_c(1, cb);
-    }
+    load_v(1, vb);
+    load_c(1, cb);
     store_v(0, va);
     store_c(0, 0, ca);
     __syncthreads();
@@ -198,28 +199,18 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
 #pragma unroll 1
   for (int s = 0; s < nslab; s += 2) {
     // even slab s in buffer 0; set b holds slab s + 1
-    if (s + 2 < nslab) {
-      load_v(s + 2, va);
-      load_c(s + 2, ca);
-    }
+    load_v(s + 2, va);
+    load_c(s + 2, ca);
     compute(0);
-    if (s + 1 < nslab) {
-      store_v(1, vb);
-      store_c(1, s + 1, cb);
-    }
+    store_v(1, vb);
+    store_c(1, s + 1, cb);
     __syncthreads();
-    if (s + 1 < nslab) {
-      if (s + 3 < nslab) {
-        load_v(s + 3, vb);
-        load_c(s + 3, cb);
-      }
-      compute(1);
-      if (s + 2 < nslab) {
-        store_v(0, va);
-        store_c(0, s + 2, ca);
-      }
-      __syncthreads();
-    }
+    load_v(s + 3, vb);
+    load_c(s + 3, cb);
+    if (s + 1 < nslab) compute(1);                    // uniform
+    store_v(0, va);
+    store_c(0, s + 2, ca);
+    __syncthreads();
   }
 
   // ---- partial sums: part[n][i][c], i = 16 f + 4 g + q ----
@@ -237,9 +228,9 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
   }
 }
 
-template <int FS>
+template <int FS, bool EVEN>
 __global__ void __launch_bounds__(512) k_r4_h16(const R4Args a) {
-  r4_body<FS>(a, blockIdx.x, blockIdx.y);
+  r4_body<FS, EVEN>(a, blockIdx.x, blockIdx.y);
 }
 
 }  // namespace sb2

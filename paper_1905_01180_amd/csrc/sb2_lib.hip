@@ -425,7 +425,10 @@ template <int FS>
 hipError_t launch_r4_fs(const ChainRefs& r, hipStream_t st) {
   const R4Args a = r4_args(r);
   StageTimer tm(3, st);
-  hipLaunchKernelGGL((k_r4_h16<FS>), dim3((unsigned)r4_tiles(a), (unsigned)r.N), dim3(512), 0, st, a);
+  if ((a.kc & 1) == 0)
+    hipLaunchKernelGGL((k_r4_h16<FS, true>), dim3((unsigned)r4_tiles(a), (unsigned)r.N), dim3(512), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_r4_h16<FS, false>), dim3((unsigned)r4_tiles(a), (unsigned)r.N), dim3(512), 0, st, a);
   return hipGetLastError();
 }
 
