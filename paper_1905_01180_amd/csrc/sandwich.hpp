@@ -97,15 +97,14 @@ struct R23Cfg {
   // groups are free of LDS bank conflicts on gfx950 (odd u halves the rate)
   static constexpr int LP = KW + 16;
   static constexpr int PI = NT;                       // producer items per lane: 16 ceil(N/4) <= 64 NT
-  static constexpr int PS = 3;                        // slabs in flight in the producer
   static_assert(LP >= KW + 8, "row padding holds one 8-slot item");
   static_assert((LP / 8) % 4 == 2, "conflict-free row pitch");
 };
 
 // Workgroup wg of nwg: tasks [ntask wg / nwg, ntask (wg + 1) / nwg).
 // Waves 0 .. NT-1 compute; wave NT (the producer) streams the A slabs: while
-// the compute waves multiply slab g it writes slab g + 1 (loaded PS slabs
-// earlier) into the free LDS buffer and loads slab g + 1 + PS.  The two roles run
+// the compute waves multiply slab g it writes slab g + 1 (loaded two slabs
+// earlier) into the free LDS buffer and loads slab g + 3.  The two roles run
 // separate loops (their registers do not overlap) with the same barrier
 // sequence: one barrier per slab, plus one after staging Gbt when NT = 1.
 template <int NT>
@@ -188,13 +187,17 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
       pcol[u] = ok ? 8 * (L - r * nc4) : KW;
       pq[u] = ok ? 4 * (L - r * nc4) : 1 << 20;
     }
-    // PS register sets: slab x is held in set x % PS between its load and its
-    // store, so PS slabs are in flight while the compute waves multiply
-    constexpr int PS = C_::PS;
-    float2 pv[PS][PI][4];                             // 4 complex per item
+    // Two register sets: slab x lives in set x % 2 between its load and its
+    // store, loaded three slabs ahead of its use, so two slabs are in flight
+    // while the compute waves multiply.  Every step issues the same memory
+    // operations (loads past the end re-read the last slab and are never
+    // stored where a compute wave reads them), so each wait covers only the
+    // set being stored.
+    float2 pa[PI][4], pb[PI][4];                      // 4 complex per item
     // loads only clamp their addresses (registers untouched until stored, so
     // the loads stay in flight); rows and q past N are zeroed when stored
     auto p_load = [&](i64 g, float2 (&v)[PI][4]) {
+      g = g < nslab ? g : nslab - 1;                  // past the end: re-read the last slab
       const i64 t = t0 + g / NT;
       const int c = (int)(g - (g / NT) * NT);
       // uniform base and 32-bit byte offsets (N^2 elements per task)
@@ -228,36 +231,34 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
         *reinterpret_cast<hx8*>(&sA[buf][1][prow[u]][pcol[u]]) = l;
       }
     };
-    // prologue: slab 0 to buffer 0; slabs 1 .. PS in flight
-    if (nslab > 0) {
-      p_load(0, pv[0]);
-      p_store(0, 0, pv[0]);
-#pragma unroll
-      for (int k = 1; k <= PS; ++k)
-        if (k < nslab) p_load(k, pv[k % PS]);
-    }
-    // the same barrier sequence as the compute waves' slab loop, unrolled by
-    // PS so that every register set index is static
     i64 cur_b = -1;
-#pragma unroll 1
-    for (i64 g0 = 0; g0 < nslab; g0 += PS) {
-#pragma unroll
-      for (int k = 0; k < PS; ++k) {
-        const i64 g = g0 + k;
-        if (g >= nslab) break;
-        __syncthreads();
-        const i64 t = t0 + g / NT;
-        const int c = (int)(g - (g / NT) * NT);
-        const i64 b = t / nn;
-        if (c == 0 && b != cur_b) {
-          stage_gbt(b);
-          cur_b = b;
-          if (NT == 1) __syncthreads();
-        }
-        const int ks = (k + 1) % PS;                  // set of slab g + 1 (g0 is a multiple of PS; static once unrolled)
-        if (g + 1 < nslab) p_store(g + 1, (int)((g + 1) & 1), pv[ks]);
-        if (g + 1 + PS < nslab) p_load(g + 1 + PS, pv[ks]);
+    // one step of the compute waves' barrier sequence: slab g is published,
+    // slab g + 1 is written to the free buffer, slab g + 3 is loaded
+    auto step = [&](i64 g, float2 (&v)[PI][4]) {
+      __syncthreads();
+      const i64 t = t0 + g / NT;
+      const int c = (int)(g - (g / NT) * NT);
+      const i64 b = t / nn;
+      if (c == 0 && b != cur_b) {
+        stage_gbt(b);
+        cur_b = b;
+        if (NT == 1) __syncthreads();
       }
+      p_store(g + 1, (int)((g + 1) & 1), v);
+      p_load(g + 3, v);
+    };
+    if (nslab > 0) {                                  // slab 0 to buffer 0; slabs 1, 2 in flight
+      p_load(0, pa);
+      p_store(0, 0, pa);
+      p_load(1, pb);
+      p_load(2, pa);
+      i64 g = 0;
+#pragma unroll 1
+      for (; g + 1 < nslab; g += 2) {
+        step(g, pb);                                  // stores slab g + 1 (odd: set b), loads g + 3
+        step(g + 1, pa);                              // stores slab g + 2 (even: set a), loads g + 4
+      }
+      if (g < nslab) step(g, pb);
     }
     if (lane == 0) red[w] = 0.f;
   } else {
