@@ -210,6 +210,15 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
           v[u][e] = *reinterpret_cast<const float2*>(base + 8u * (ro + (unsigned)min(pq[u] + e, N - 1)));
       }
     };
+    // split scale per element: 2^xA inside the block, 0 for q past N (zeroes
+    // the element through the product, so that hi = f16(x s) and
+    // lo = f16(x s - hi) map to one multiply, one conversion and one mixed
+    // fused multiply-add per value)
+    float sq[PI][4];
+#pragma unroll
+    for (int u = 0; u < PI; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sq[u][e] = pq[u] + e < N ? sAs : 0.f;
     auto p_store = [&](i64 g, int buf, const float2 (&v)[PI][4]) {
       const int c = (int)(g - (g / NT) * NT);
 #pragma unroll
@@ -218,10 +227,10 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
         hx8 h, l;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const bool ok = rowok && pq[u] + e < N;
+          const float se = rowok ? sq[u][e] : 0.f;
           _Float16 xh, xl, yh, yl;
-          split_h(ok ? v[u][e].x * sAs : 0.f, xh, xl);
-          split_h(ok ? v[u][e].y * sAs : 0.f, yh, yl);
+          split_h(v[u][e].x * se, xh, xl);
+          split_h(v[u][e].y * se, yh, yl);
           h[e] = xh;
           l[e] = xl;
           h[4 + e] = yh;
