@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(64 * (NT + 1)) k_r23_group(const ChainRefs* __
   const long long b = blockIdx.x;
   const int i = sub_member(t, b);
   const R23Args a = r23_args(refs[t.idx[i]]);
-  r23_body<NT>(a, (int)(b - t.off[i]), (int)(t.off[i + 1] - t.off[i]));
+  r23_body<NT, false>(a, (int)(b - t.off[i]), (int)(t.off[i + 1] - t.off[i]));   // members of any parity
 }
 
 template <int FS>

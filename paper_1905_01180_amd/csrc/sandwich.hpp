@@ -42,6 +42,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gemm.hpp"
 
 namespace sb2 {
@@ -107,7 +109,7 @@ struct R23Cfg {
 // earlier) into the free LDS buffer and loads slab g + 3.  The two roles run
 // separate loops (their registers do not overlap) with the same barrier
 // sequence: one barrier per slab, plus one after staging Gbt when NT = 1.
-template <int NT>
+template <int NT, bool EVEN>
 __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
   using C_ = R23Cfg<NT>;
   constexpr int KW = C_::KW, LP = C_::LP, NTH = C_::NTH, PI = C_::PI;
@@ -205,9 +207,18 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
 #pragma unroll
       for (int u = 0; u < PI; ++u) {
         const unsigned ro = (unsigned)(min(16 * c + prow[u], N - 1) * N);
+        if constexpr (EVEN) {                         // 16-byte aligned complex pairs (N even)
+          const float4 f0 = *reinterpret_cast<const float4*>(base + 8u * (ro + (unsigned)min(pq[u], N - 2)));
+          const float4 f1 = *reinterpret_cast<const float4*>(base + 8u * (ro + (unsigned)min(pq[u] + 2, N - 2)));
+          v[u][0] = make_float2(f0.x, f0.y);
+          v[u][1] = make_float2(f0.z, f0.w);
+          v[u][2] = make_float2(f1.x, f1.y);
+          v[u][3] = make_float2(f1.z, f1.w);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          v[u][e] = *reinterpret_cast<const float2*>(base + 8u * (ro + (unsigned)min(pq[u] + e, N - 1)));
+          for (int e = 0; e < 4; ++e)
+            v[u][e] = *reinterpret_cast<const float2*>(base + 8u * (ro + (unsigned)min(pq[u] + e, N - 1)));
+        }
       }
     };
     // split scale per element: 2^xA inside the block, 0 for q past N (zeroes
@@ -219,15 +230,14 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
     for (int u = 0; u < PI; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) sq[u][e] = pq[u] + e < N ? sAs : 0.f;
-    auto p_store = [&](i64 g, int buf, const float2 (&v)[PI][4]) {
-      const int c = (int)(g - (g / NT) * NT);
+    auto p_store_rows = [&](auto all_rows, int c, int buf, const float2 (&v)[PI][4]) {
 #pragma unroll
       for (int u = 0; u < PI; ++u) {
-        const bool rowok = 16 * c + prow[u] < N;
+        const bool rowok = decltype(all_rows)::value || 16 * c + prow[u] < N;
         hx8 h, l;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const float se = rowok ? sq[u][e] : 0.f;
+          const float se = decltype(all_rows)::value ? sq[u][e] : (rowok ? sq[u][e] : 0.f);
           _Float16 xh, xl, yh, yl;
           split_h(v[u][e].x * se, xh, xl);
           split_h(v[u][e].y * se, yh, yl);
@@ -239,6 +249,12 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
         *reinterpret_cast<hx8*>(&sA[buf][0][prow[u]][pcol[u]]) = h;
         *reinterpret_cast<hx8*>(&sA[buf][1][prow[u]][pcol[u]]) = l;
       }
+    };
+    // slabs inside the block (16 c + 16 <= N) need no row test
+    auto p_store = [&](i64 g, int buf, const float2 (&v)[PI][4]) {
+      const int c = (int)(g - (g / NT) * NT);
+      if (16 * c + 16 <= N) p_store_rows(std::true_type{}, c, buf, v);   // uniform
+      else p_store_rows(std::false_type{}, c, buf, v);
     };
     i64 cur_b = -1;
     // one step of the compute waves' barrier sequence: slab g is published,
@@ -419,9 +435,9 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
   }
 }
 
-template <int NT>
+template <int NT, bool EVEN>
 __global__ void __launch_bounds__(64 * (NT + 1)) k_r23_h16(const R23Args a) {
-  r23_body<NT>(a, blockIdx.x, gridDim.x);
+  r23_body<NT, EVEN>(a, blockIdx.x, gridDim.x);
 }
 
 }  // namespace sb2

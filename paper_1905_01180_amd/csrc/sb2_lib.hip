@@ -398,7 +398,10 @@ template <int NT>
 hipError_t launch_r23_nt(const ChainRefs& r, int nwg, hipStream_t st) {
   const R23Args a = r23_args(r);
   StageTimer tm(1, st);
-  hipLaunchKernelGGL((k_r23_h16<NT>), dim3(nwg), dim3(R23Cfg<NT>::NTH), 0, st, a);
+  if (r.N % 2 == 0)
+    hipLaunchKernelGGL((k_r23_h16<NT, true>), dim3(nwg), dim3(R23Cfg<NT>::NTH), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_r23_h16<NT, false>), dim3(nwg), dim3(R23Cfg<NT>::NTH), 0, st, a);
   return hipGetLastError();
 }
 
