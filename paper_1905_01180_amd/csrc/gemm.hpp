@@ -36,6 +36,7 @@ typedef long long i64;
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 hx8 __attribute__((ext_vector_type(8)));
+typedef unsigned ux4 __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
   int M, N, K;
@@ -88,6 +89,24 @@ __device__ __forceinline__ fx4 mma3(hx8 ah, hx8 al, hx8 bh, hx8 bl, fx4 c) {
   c = mma16(al, bh, c);
   c = mma16(ah, bl, c);
   return mma16(ah, bh, c);
+}
+
+// Split of two scaled values x0 s0, x1 s1 into packed float16 pairs
+// h = [f16(x0 s0), f16(x1 s1)] and l = [f16(x0 s0 - h0), f16(x1 s1 - h1)].
+// Each half is one mixed-precision fused multiply-add that rounds once to
+// float16 (the low-part one takes its h operand as a float16 half of h), so a
+// pair costs four instructions.  With s a power of two or zero, x s is exact
+// in float32 and the halves equal f16(x s) and f16(x s - f16(x s)).
+// The compiler does not insert matrix-core wait states around inline
+// assembly: the inputs must not be fresh MFMA results and the outputs must not
+// feed an MFMA directly (here they come from memory loads and go to LDS).
+__device__ __forceinline__ void split_pair(float x0, float s0, float x1, float s1, unsigned& h, unsigned& l) {
+  asm("v_fma_mixlo_f16 %0, %2, %3, 0\n\t"
+      "v_fma_mixhi_f16 %0, %4, %5, 0\n\t"
+      "v_fma_mixlo_f16 %1, %2, %3, -%0 op_sel_hi:[0,0,1]\n\t"
+      "v_fma_mixhi_f16 %1, %4, %5, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+      : "=&v"(h), "=&v"(l)
+      : "v"(x0), "v"(s0), "v"(x1), "v"(s1));
 }
 
 template <typename V> __device__ __forceinline__ V vzero() {

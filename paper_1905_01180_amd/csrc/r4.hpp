@@ -122,20 +122,14 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
 #pragma unroll
     for (int e = 0; e < PC; ++e) {
       const int cl = 8 * w + 2 * e + chalf;
-      _Float16 rh0, rl0, ih0, il0, rh1, rl1, ih1, il1;
-      {
-        const float x = src[e].x * m0, y = src[e].y * m0, u = src[e].z * m1, t = src[e].w * m1;
-        rh0 = (_Float16)x; rl0 = (_Float16)(x - (float)rh0);
-        ih0 = (_Float16)y; il0 = (_Float16)(y - (float)ih0);
-        rh1 = (_Float16)u; rl1 = (_Float16)(u - (float)rh1);
-        ih1 = (_Float16)t; il1 = (_Float16)(t - (float)ih1);
-      }
-      typedef _Float16 hx2 __attribute__((ext_vector_type(2)));
-      hx2 v;
-      v[0] = rh0; v[1] = rh1; *reinterpret_cast<hx2*>(&sC[buf][0][cl][ck]) = v;
-      v[0] = rl0; v[1] = rl1; *reinterpret_cast<hx2*>(&sC[buf][1][cl][ck]) = v;
-      v[0] = ih0; v[1] = ih1; *reinterpret_cast<hx2*>(&sC[buf][2][cl][ck]) = v;
-      v[0] = il0; v[1] = il1; *reinterpret_cast<hx2*>(&sC[buf][3][cl][ck]) = v;
+      // packed pairs (k, k + 1) of the real and imaginary hi and lo parts
+      unsigned rh, rl, ih, il;
+      split_pair(src[e].x, m0, src[e].z, m1, rh, rl);
+      split_pair(src[e].y, m0, src[e].w, m1, ih, il);
+      *reinterpret_cast<unsigned*>(&sC[buf][0][cl][ck]) = rh;
+      *reinterpret_cast<unsigned*>(&sC[buf][1][cl][ck]) = rl;
+      *reinterpret_cast<unsigned*>(&sC[buf][2][cl][ck]) = ih;
+      *reinterpret_cast<unsigned*>(&sC[buf][3][cl][ck]) = il;
     }
   };
 

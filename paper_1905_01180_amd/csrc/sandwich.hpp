@@ -74,7 +74,6 @@ __device__ __forceinline__ int split_exp(float m, int& e, bool& ok) {
 
 // [x_re(4), x_im(4)] -> [x_im(4), -x_re(4)] (sign flips are exact)
 __device__ __forceinline__ hx8 swap_neg(hx8 x) {
-  typedef unsigned ux4 __attribute__((ext_vector_type(4)));
   const ux4 u = __builtin_bit_cast(ux4, x);
   ux4 r;
   r[0] = u[2];
@@ -222,9 +221,8 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
       }
     };
     // split scale per element: 2^xA inside the block, 0 for q past N (zeroes
-    // the element through the product, so that hi = f16(x s) and
-    // lo = f16(x s - hi) map to one multiply, one conversion and one mixed
-    // fused multiply-add per value)
+    // the element through the product, so that each half of the split is one
+    // mixed fused multiply-add)
     float sq[PI][4];
 #pragma unroll
     for (int u = 0; u < PI; ++u)
@@ -234,20 +232,17 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
 #pragma unroll
       for (int u = 0; u < PI; ++u) {
         const bool rowok = decltype(all_rows)::value || 16 * c + prow[u] < N;
-        hx8 h, l;
+        float se[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float se = decltype(all_rows)::value ? sq[u][e] : (rowok ? sq[u][e] : 0.f);
-          _Float16 xh, xl, yh, yl;
-          split_h(v[u][e].x * se, xh, xl);
-          split_h(v[u][e].y * se, yh, yl);
-          h[e] = xh;
-          l[e] = xl;
-          h[4 + e] = yh;
-          l[4 + e] = yl;
-        }
-        *reinterpret_cast<hx8*>(&sA[buf][0][prow[u]][pcol[u]]) = h;
-        *reinterpret_cast<hx8*>(&sA[buf][1][prow[u]][pcol[u]]) = l;
+        for (int e = 0; e < 4; ++e) se[e] = decltype(all_rows)::value ? sq[u][e] : (rowok ? sq[u][e] : 0.f);
+        // [re(4), im(4)] as packed pairs
+        unsigned h[4], l[4];
+        split_pair(v[u][0].x, se[0], v[u][1].x, se[1], h[0], l[0]);
+        split_pair(v[u][2].x, se[2], v[u][3].x, se[3], h[1], l[1]);
+        split_pair(v[u][0].y, se[0], v[u][1].y, se[1], h[2], l[2]);
+        split_pair(v[u][2].y, se[2], v[u][3].y, se[3], h[3], l[3]);
+        *reinterpret_cast<ux4*>(&sA[buf][0][prow[u]][pcol[u]]) = ux4{h[0], h[1], h[2], h[3]};
+        *reinterpret_cast<ux4*>(&sA[buf][1][prow[u]][pcol[u]]) = ux4{l[0], l[1], l[2], l[3]};
       }
     };
     // slabs inside the block (16 c + 16 <= N) need no row test
