@@ -46,7 +46,6 @@ __host__ __device__ inline R4Args r4_args(const ChainRefs& r) {
   a.xmax = r.scal + S_CMAX;
   return a;
 }
-__host__ __device__ inline int r4_tiles(const R4Args& a) { return (a.ncol + 63) / 64; }
 
 // Members of one bucket: refs index and workgroup range of each.
 struct SubGroup {

@@ -40,6 +40,9 @@ struct R4Args {
   const unsigned* xmax;
 };
 
+// column tiles of 64 columns
+__host__ __device__ inline int r4_tiles(const R4Args& a) { return (a.ncol + 63) / 64; }
+
 // Workgroup (bx, by): columns 64 bx .., chunk by.  EVEN: the chunk length
 // kc is even (complex pairs of C are 16-byte aligned).
 template <int FS, bool EVEN>

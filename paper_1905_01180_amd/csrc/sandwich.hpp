@@ -72,17 +72,6 @@ __device__ __forceinline__ int split_exp(float m, int& e, bool& ok) {
   return 14 - e;
 }
 
-// [x_re(4), x_im(4)] -> [x_im(4), -x_re(4)] (sign flips are exact)
-__device__ __forceinline__ hx8 swap_neg(hx8 x) {
-  const ux4 u = __builtin_bit_cast(ux4, x);
-  ux4 r;
-  r[0] = u[2];
-  r[1] = u[3];
-  r[2] = u[0] ^ 0x80008000u;
-  r[3] = u[1] ^ 0x80008000u;
-  return __builtin_bit_cast(hx8, r);
-}
-
 __device__ __forceinline__ void split_h(float x, _Float16& hi, _Float16& lo) {
   hi = (_Float16)x;
   lo = (_Float16)(x - (float)hi);
@@ -264,8 +253,12 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
         cur_b = b;
         if (NT == 1) __syncthreads();
       }
+      // the producer's stores and loads gate the next slab: they take issue
+      // priority over the compute wave that shares its SIMD
+      __builtin_amdgcn_s_setprio(2);
       p_store(g + 1, (int)((g + 1) & 1), v);
       p_load(g + 3, v);
+      __builtin_amdgcn_s_setprio(0);
     };
     if (nslab > 0) {                                  // slab 0 to buffer 0; slabs 1, 2 in flight
       p_load(0, pa);
@@ -292,11 +285,10 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
     const float unscale = ldexpf(1.f, -xGb - xY);
     const int p = 16 * w + lr;                        // this lane's index p in step 1
 
-    // B operand of step 1 for chunk c: [G_re, -G_im] at q = 16c + 4g + 0..3
-    // of row p; hi and lo.  It serves both output parts: the real part pairs
-    // it with the A fragment [A_re, A_im], the imaginary part with the swapped
-    // fragment [A_im, -A_re].
-    hx8 bre_h[NT], bre_l[NT];
+    // B operands of step 1 for chunk c at q = 16c + 4g + 0..3 of row p, hi
+    // and lo: [G_re, -G_im] for the real part and [G_im, G_re] for the
+    // imaginary part, both paired with the A fragment [A_re, A_im]
+    hx8 bre_h[NT], bre_l[NT], bim_h[NT], bim_l[NT];
     auto load_g = [&](i64 b) {
       const float2* G = reinterpret_cast<const float2*>(a.Gs) + b * nn;
 #pragma unroll
@@ -313,6 +305,10 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
           bre_l[c][e] = rl;
           bre_h[c][4 + e] = -ih;
           bre_l[c][4 + e] = -il;
+          bim_h[c][e] = ih;
+          bim_l[c][e] = il;
+          bim_h[c][4 + e] = rh;
+          bim_l[c][4 + e] = rl;
         }
       }
     };
@@ -364,10 +360,7 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
     };
 
     for_slabs(load_g, [&](i64 t, i64 b, int c, i64, int buf) {
-      // Gbt fragments of the previous slab's step 2, read ahead of step 1 so
-      // that their latency is hidden behind its products
-      hx8 gh[NT], gl[NT];
-      if (c > 0) read_g2(c - 1, gh, gl);
+      hx8 gh[NT], gl[NT];                             // Gbt fragments of step 2
       __builtin_amdgcn_sched_barrier(0);
       // step 1: Y^T rows 16c .. 16c+15, column p
       fx4 yr = vzero<fx4>(), yi = vzero<fx4>();
@@ -382,15 +375,20 @@ __device__ __forceinline__ void r23_body(const R23Args& a, int wg, int nwg) {
           nl = *reinterpret_cast<const hx8*>(arow + PL + 32 * (qc + 1));
         }
         yr = mma3(ah, al, bre_h[qc], bre_l[qc], yr);
-        yi = mma3(swap_neg(ah), swap_neg(al), bre_h[qc], bre_l[qc], yi);
+        yi = mma3(ah, al, bim_h[qc], bim_l[qc], yi);
         if (qc + 1 < NT) {
           ah = nh;
           al = nl;
         }
       }
       // step 2 of the previous slab: its products keep the matrix cores busy
-      // while this slab's step-1 results drain and are split
-      if (c > 0) step2(gh, gl);
+      // while this slab's step-1 results drain and are split; its Gbt
+      // fragments are read here rather than ahead of step 1, which keeps
+      // fewer registers live
+      if (c > 0) {
+        read_g2(c - 1, gh, gl);
+        step2(gh, gl);
+      }
       split_y(yr, yi);
       if (c + 1 < NT) return;
       read_g2(NT - 1, gh, gl);

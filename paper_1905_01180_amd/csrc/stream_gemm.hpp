@@ -554,7 +554,19 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int grp = lane >> 4, lr = lane & 15;
-  const int ts = bx % g.tiles_m, pp = bx / g.tiles_m;
+  // workgroup bx -> (shared-operand tile ts, first streamed tile pp).  Launch
+  // order deals workgroups to the 8 XCDs round-robin (bx % 8); when npersist
+  // is a multiple of 8, all tiles_m workgroups of one pp (which stream the
+  // same X tiles) are placed on one XCD, whose L2 then serves the X re-reads
+  int ts, pp;
+  if (npersist % 8 == 0) {
+    const int slot = bx >> 3;
+    ts = slot % g.tiles_m;
+    pp = 8 * (slot / g.tiles_m) + (bx & 7);
+  } else {
+    ts = bx % g.tiles_m;
+    pp = bx / g.tiles_m;
+  }
   const int s0 = ts * SR;
   const int slim = SA ? g.M : g.N;
   const int xlim = SA ? g.N : g.M;
