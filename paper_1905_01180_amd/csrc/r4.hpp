@@ -8,7 +8,7 @@
 // (real) arrives pre-split as two float16 planes; C (complex float32) is split
 // once, when it is staged.  The N chunks are summed in float64 afterwards;
 // within a chunk the float32 MFMA accumulators are folded into float64 once per
-// slab.
+// two slabs.
 //
 // Workgroup: 8 waves = 2 row halves x 4 column groups (two waves per SIMD),
 // 64 columns c; wave (h, g) owns the 16 columns 16 g .. 16 g + 15 and the row
@@ -166,7 +166,11 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
         }
       }
     }
-    // fold the slab's float32 sums into float64
+  };
+  // fold the float32 sums into float64, once per two slabs (128 k: each
+  // float32 partial takes 12 MFMA accumulations, against the 2^-22 relative
+  // error of a split operand)
+  auto fold = [&]() {
 #pragma unroll
     for (int f = 0; f < FH; ++f)
 #pragma unroll
@@ -205,6 +209,7 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
     load_v(s + 3, vb);
     load_c(s + 3, cb);
     if (s + 1 < nslab) compute(1);                    // uniform
+    fold();
     store_v(0, va);
     store_c(0, s + 2, ca);
     __syncthreads();
