@@ -255,7 +255,8 @@ const char* sb2_status_string(int status);
  * of past times one pass of the contraction chain holds).  ws must hold
  * sb2_workspace_size(SB2_OP_AUTOTUNE, N, T, prec) bytes; its contents are
  * scratch.  Searched, one after the other: the number of workgroups of the
- * single-slab contraction launches (256 .. 3072, default 768), the split-K
+ * single-slab contraction launches (256 .. 3072; default 3072 for
+ * SB2_SPLIT_FP16, 768 otherwise), the split-K
  * factor of the last contraction (50 .. 200 % of the default count) and, for
  * SB2_SPLIT_FP16 with N <= 112, the number of workgroups of the fused second
  * and third contraction (256 .. 2048, default 512).  The winner goes into a

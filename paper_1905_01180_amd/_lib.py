@@ -322,8 +322,13 @@ def sb2_autotune(v, h, rho_hist, dt, prec="fp16x3"):
 
 
 DEFAULT_TUNING = {"persist": 768, "r4pct": 100, "fused": 512}
+DEFAULT_PERSIST_FP16X3 = 3072          # the library's default for split float16
 
 
-def sb2_set_tuning(n: int, prec, persist: int = 768, r4pct: int = 100, fused: int = 512):
-    """Install launch parameters for (n, prec), e.g. from an earlier sb2_autotune."""
-    _call("sb2_set_tuning", n, _prec(prec), persist, r4pct, fused)
+def sb2_set_tuning(n: int, prec, persist: int = None, r4pct: int = 100, fused: int = 512):
+    """Install launch parameters for (n, prec), e.g. from an earlier
+    sb2_autotune; persist=None takes the library's default for prec."""
+    p = _prec(prec)
+    if persist is None:
+        persist = DEFAULT_PERSIST_FP16X3 if p == PRECISIONS["fp16x3"] else DEFAULT_TUNING["persist"]
+    _call("sb2_set_tuning", n, p, persist, r4pct, fused)
