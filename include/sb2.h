@@ -158,7 +158,7 @@ int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const v
                          double dt, void* I_out, void* Sigma_out, void* ws, size_t ws_bytes, void* stream);
 
 /* 8-fold packed interaction tensor.  For real basis functions the Coulomb
- * integrals of Eq. 3 obey the 8-point symmetry of Eq. 6: v_ijkl depends only
+ * integrals of Eq. 3 obey the 8-point symmetry of Eq. 4: v_ijkl depends only
  * on the unordered pairs {i, l} (both orbitals at r) and {j, k} (at r') and
  * is unchanged when the two pairs are exchanged.  Packed storage keeps one
  * float64 per orbit:

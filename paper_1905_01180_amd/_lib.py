@@ -2,7 +2,7 @@
 
 Every computation runs in the HIP library; this module checks tensor shapes,
 dtypes and devices, hands device pointers and the current HIP stream to the
-C ABI and keeps one reusable device workspace per device.  It fails loudly if
+C ABI and keeps one reusable device workspace per (device, stream).  It fails loudly if
 the library is not built: there is no CPU fallback.
 """
 from __future__ import annotations
@@ -106,21 +106,68 @@ def _stream(dev: torch.device) -> int:
     return torch.cuda.current_stream(dev).cuda_stream
 
 
-_ws = {}
+class WorkspaceCache:
+    """Reusable device workspaces, one per (device, stream).
+
+    Calls that share a workspace must be ordered on one stream, so the cache
+    keys its buffers by the device index and the HIP stream the call is
+    enqueued on: calls on two streams never share scratch memory.  Each use
+    marks the buffer as in use on that stream (`record_stream`), so when an
+    outgrown buffer is dropped the caching allocator does not hand its memory
+    to other work before that stream has finished with it.  A buffer used
+    while the stream was being captured into a HIP graph is never dropped on
+    growth (the graph keeps its raw pointer and may be replayed later); it is
+    retired and stays alive until `clear()`, which may only be called when no
+    such graph will be replayed again.
+    """
+
+    def __init__(self, alloc=None):
+        self._alloc = alloc or (lambda nbytes, dev: torch.empty(nbytes, dtype=torch.uint8, device=dev))
+        self._bufs = {}
+        self._captured = set()     # keys whose current buffer a graph capture used
+        self._retired = []
+
+    def get(self, nbytes: int, dev, key_dev: int, key_stream: int, stream=None, capturing: bool = False):
+        key = (key_dev, key_stream)
+        buf = self._bufs.get(key)
+        if buf is None or buf.numel() < nbytes:
+            if buf is not None and key in self._captured:
+                self._retired.append(buf)
+            self._captured.discard(key)
+            buf = self._alloc(max(int(nbytes), 256), dev)
+            self._bufs[key] = buf
+        if capturing:
+            self._captured.add(key)            # kept alive for replays; no stream bookkeeping under capture
+        elif stream is not None and hasattr(buf, "record_stream"):
+            buf.record_stream(stream)
+        return buf
+
+    def clear(self):
+        self._bufs.clear()
+        self._captured.clear()
+        self._retired.clear()
+
+    @property
+    def retired(self):
+        return len(self._retired)
+
+    def __len__(self):
+        return len(self._bufs)
+
+
+_ws = WorkspaceCache()
 
 
 def workspace(nbytes: int, dev: torch.device) -> torch.Tensor:
-    """A cached device buffer of at least nbytes (grown, never shrunk)."""
-    key = dev.index if dev.index is not None else torch.cuda.current_device()
-    buf = _ws.get(key)
-    if buf is None or buf.numel() < nbytes:
-        _ws.pop(key, None)
-        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
-        _ws[key] = buf
-    return buf
+    """A cached device buffer of at least nbytes for the current stream of dev."""
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    st = torch.cuda.current_stream(idx)
+    return _ws.get(nbytes, dev, idx, st.cuda_stream, st, torch.cuda.is_current_stream_capturing())
 
 
 def release_workspace():
+    """Free every cached workspace (including those outgrown); no captured
+    graph that used them may be replayed afterwards."""
     _ws.clear()
 
 

@@ -557,7 +557,7 @@ __global__ void k_real_to_c(i64 n, const double* __restrict__ x, cplx* __restric
 }
 
 // ---------------------------------------------------------------------------
-// 8-fold packed interaction tensor (real orbitals, Eq. 6): v_ijkl depends only
+// 8-fold packed interaction tensor (real orbitals, Eq. 4): v_ijkl depends only
 // on the unordered pairs {i, l} (the orbitals at r) and {j, k} (at r') and on
 // their order, so it is stored once per unordered pair of unordered pairs:
 //   pair(a, b) = max(a,b) (max(a,b) + 1) / 2 + min(a,b),

@@ -11,11 +11,17 @@ Structure of the inputs (the paper's model, Sec. II):
               X_ij = a + ib, a, b ~ N(0, 1): E|h_ij|^2 = 1 off the diagonal and a
               real N(0, 1) diagonal.
   * v      -- real two-body tensor v_ijkl (Eq. 3).  For a real basis it has the
-              8-fold permutation symmetry of Eq. 4; the generator builds a dense
-              tensor with the sub-group {ijkl, jilk, klij, lkji} of it:
-              X_ijkl = sum_g A_ig A_jg B_kg B_lg, v = (X + X_klij)/2, scaled to
-              max|v| = 0.5.  A "generic" variant averages an i.i.d. Gaussian
-              tensor over that sub-group instead (no low-rank structure).
+              8-fold permutation symmetry of Eq. 4 (pairs {i, l} and {j, k}).
+              "lowrank" (the workloads' default, the construction the workloads
+              name): X_ijkl = sum_g A_ig A_jg B_kg B_lg, v = (X + X_klij)/2,
+              scaled to max|v| = 0.5.  It has {ijkl, jilk, klij, lkji} but also
+              i <-> j alone and k <-> l alone, which are NOT symmetries of Eq. 4;
+              with them the exchange term of Eq. 13 is exactly -1/2 of the direct
+              term, so checks that must separate the two use one of the others:
+              "generic" averages an i.i.d. Gaussian tensor over {ijkl, jilk,
+              klij, lkji} (no low-rank structure, no i <-> j symmetry), and
+              "orbitals" builds Coulomb-like integrals of real orthonormal
+              functions on a grid (exactly the 8-fold symmetry of Eq. 4).
   * rho    -- one-particle density matrix, Hermitian with eigenvalues in [0, 1]
               and trace N/2 (rho = -i G^<(t,t), Sec. II).  Eigenvalues come in
               pairs (u, 1-u) with u ~ U[0,1] (plus 0.5 when N is odd), rotated by
@@ -53,7 +59,12 @@ def hermitian_gaussian(n: int, g: np.random.Generator) -> np.ndarray:
 
 
 def interaction_lowrank(n: int, g: np.random.Generator, vmax: float = 0.5) -> np.ndarray:
-    """Dense real v_ijkl with v_ijkl = v_jilk = v_klij = v_lkji, max|v| = vmax."""
+    """Dense real v_ijkl with v_ijkl = v_jilk = v_klij = v_lkji, max|v| = vmax.
+
+    Also symmetric under i <-> j alone and k <-> l alone (not symmetries of
+    real-orbital integrals): then 2 v_mqsj - v_qmsj = v_mqsj, and the exchange
+    term of Eq. 13 is exactly -1/2 of the direct term.  Index-order checks of
+    the exchange term need interaction_generic or interaction_real_orbitals."""
     a = g.standard_normal((n, n))
     b = g.standard_normal((n, n))
     aa = (a[:, None, :] * a[None, :, :]).reshape(n * n, n)      # (ij, g)
@@ -146,7 +157,14 @@ def make_system(n: int, t: int, config_id: int = 0, system_id: int = 0, dt: floa
                 v_kind: str = "lowrank", hist_kind: str = "smooth") -> System:
     h = hermitian_gaussian(n, rng(config_id, system_id, _S_H))
     gv = rng(config_id, system_id, _S_V)
-    v = interaction_lowrank(n, gv) if v_kind == "lowrank" else interaction_generic(n, gv)
+    if v_kind == "lowrank":
+        v = interaction_lowrank(n, gv)
+    elif v_kind == "generic":
+        v = interaction_generic(n, gv)
+    elif v_kind == "orbitals":
+        v = interaction_real_orbitals(n, gv)
+    else:
+        raise ValueError(f"unknown interaction kind {v_kind!r}")
     hist = rho_history(n, t, dt, rng(config_id, system_id, _S_HIST), hist_kind)
     return System(n=n, t=t, dt=dt, h=h, v=v, rho_hist=hist)
 

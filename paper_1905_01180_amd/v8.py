@@ -1,7 +1,7 @@
 """8-fold packed storage of a real interaction tensor (host side).
 
 For real basis functions the Coulomb integrals (Eq. 3) obey the 8-point
-symmetry of Eq. 6: v_ijkl depends only on the unordered pairs {i, l} and
+symmetry of Eq. 4: v_ijkl depends only on the unordered pairs {i, l} and
 {j, k} and is unchanged when the two pairs are exchanged, so about N^4 / 8
 values determine it.  Packed index (the same as the library's
 sb2_v8_expand):

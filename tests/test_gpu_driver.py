@@ -15,7 +15,7 @@ from paper_1905_01180_amd import inputs as gen
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 DT = 0.05
-TOL = {"fp64": 1e-11, "fp32": 2e-5, "fp16x3": 2e-6}
+TOL = {"fp64": 1e-11, "fp32": 2e-6, "fp16x3": 2e-6}
 
 
 def relf(a, b):
@@ -68,7 +68,7 @@ def test_first_step_hf_only(n):
     assert np.abs(st["i"][0]).max() == 0.0
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
 @pytest.mark.parametrize("hf,coll", [(True, True), (False, True), (True, False)])
 @pytest.mark.parametrize("n", [4, 17])
 def test_propagation_matches_oracle(n, hf, coll, prec):
@@ -86,8 +86,9 @@ def test_propagation_matches_oracle(n, hf, coll, prec):
     for k in range(steps):
         assert relf(st["u"][k], ref["u"][k]) < u_tol
     if coll:
-        for m in range(1, steps):
-            assert relf(st["i"][m], ref["i"][m]) < (1e-10 if prec == "fp64" else 2e-5)
+        ierr = [relf(st["i"][m], ref["i"][m]) for m in range(1, steps)]
+        print(f"propagate N={n} hf={hf} coll={coll} {prec}: I rel max {max(ierr):.2e}", flush=True)
+        assert max(ierr) < (1e-10 if prec == "fp64" else 2e-5)
     else:
         assert np.abs(st["i"]).max() == 0.0
     # the propagated density stays Hermitian with its trace; the trace moves by

@@ -1,5 +1,5 @@
 """8-fold packed interaction tensor: the format against brute-force orbits of
-the symmetry group of Eq. 6 (host), and the library's expansion (GPU)."""
+the symmetry group of Eq. 4 (host), and the library's expansion (GPU)."""
 import itertools
 
 import numpy as np
@@ -13,7 +13,7 @@ FAKE = 0x1000
 
 
 def _images(i, j, k, l):
-    # the eight index orders of Eq. 6 that leave a real Coulomb integral unchanged
+    # the eight index orders of Eq. 4 that leave a real Coulomb integral unchanged
     return {(i, j, k, l), (j, i, l, k), (k, l, i, j), (l, k, j, i),
             (i, k, j, l), (l, j, k, i), (k, i, l, j), (j, l, i, k)}
 
