@@ -52,7 +52,9 @@ typedef enum {
   SB2_ESHAPE = -2,       /* N or T out of range                                     */
   SB2_EWORKSPACE = -3,   /* ws_bytes smaller than sb2_workspace_size(...)           */
   SB2_EHIP = -4,         /* a HIP runtime call or kernel launch failed              */
-  SB2_EUNSUPPORTED = -5  /* precision not available for this entry point            */
+  SB2_EUNSUPPORTED = -5, /* precision not available for this entry point            */
+  SB2_ESCRATCH = -6      /* sb2_collision_noalloc: problem too large for its static
+                            scratch buffer                                          */
 } sb2_status;
 
 typedef enum {
@@ -126,6 +128,25 @@ int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_
 int sb2_collision_backward(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
                            const void* gI, double* gv, void* gh, void* grho,
                            int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* sb2_collision_noalloc -- sb2_collision for callers that cannot allocate
+ * device memory (code under HIP graph capture that must not allocate, tight
+ * serving loops, harnesses that forbid hipMalloc): no workspace argument, no
+ * allocation of any kind.  Its scratch memory is one static device buffer of
+ * SB2_NOALLOC_SCRATCH_BYTES per device, held from the library's first use on
+ * that device until the process ends; the chunk of past times one pass of the
+ * contraction chain holds is the largest whose workspace fits it (results
+ * equal sb2_collision's up to the order of float32 accumulation).
+ * Arguments and outputs as for sb2_collision.  Every call on a device shares
+ * that device's buffer: calls that overlap on one device (other streams,
+ * other host threads) race and give wrong results; calls ordered on one
+ * stream are safe (each call initialises what it reads).
+ * Errors: as sb2_collision; SB2_ESCRATCH (nothing enqueued) when even one
+ * past time per pass needs more than SB2_NOALLOC_SCRATCH_BYTES (about N > 40
+ * for SB2_FP32 / SB2_SPLIT_FP16, N > 32 for SB2_FP64).                       */
+#define SB2_NOALLOC_SCRATCH_BYTES (128u << 20)
+int sb2_collision_noalloc(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
+                          void* I_out, void* Sigma_out, int prec, void* stream);
 
 /* sb2_collision_prop -- sb2_collision with the propagators supplied by the
  * caller: U_hist[k] = U(t, t_k), k = 0..T-1 (T x N x N complex), the HF

@@ -24,7 +24,7 @@ OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "auto
 VERTICES = {"diagonal": 1, "symmetric": 2}
 PROP_HF, PROP_COLLISION = 1, 2
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
-          -5: "SB2_EUNSUPPORTED"}
+          -5: "SB2_EUNSUPPORTED", -6: "SB2_ESCRATCH"}
 
 _lib = None
 _lock = threading.Lock()
@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_set_tuning.argtypes = [_i, _i, _i, _i, _i]
         L.sb2_rho_step.restype = _i
         L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
+        L.sb2_collision_noalloc.restype = _i
+        L.sb2_collision_noalloc.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp]
         L.sb2_collision_prop.restype = _i
         L.sb2_collision_prop.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
         L.sb2_v8_count.restype = _sz
@@ -221,6 +223,23 @@ def sb2_collision(v: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: 
     sig = torch.empty((2, t, n, n), dtype=torch.complex128, device=v.device) if return_sigma else None
     _call("sb2_collision", n, t, v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt), out.data_ptr(),
           sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(), _stream(v.device))
+    return (out, sig) if return_sigma else out
+
+
+def sb2_collision_noalloc(v: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: float, prec="fp64",
+                          return_sigma: bool = False):
+    """sb2_collision through the allocation-free entry point: the library's
+    static per-device scratch buffer instead of a workspace (problems that do
+    not fit it raise SB2_ESCRATCH)."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    p = _prec(prec)
+    out = torch.empty((n, n), dtype=torch.complex128, device=v.device)
+    sig = torch.empty((2, t, n, n), dtype=torch.complex128, device=v.device) if return_sigma else None
+    _call("sb2_collision_noalloc", n, t, v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt),
+          out.data_ptr(), sig.data_ptr() if sig is not None else None, p, _stream(v.device))
     return (out, sig) if return_sigma else out
 
 

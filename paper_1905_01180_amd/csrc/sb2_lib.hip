@@ -20,6 +20,7 @@
 #include <cstring>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -1199,6 +1200,9 @@ const char* sb2_status_string(int status) {
     case SB2_EWORKSPACE: return "workspace smaller than sb2_workspace_size()";
     case SB2_EHIP: return "HIP runtime error while enqueueing work";
     case SB2_EUNSUPPORTED: return "precision not supported by this entry point";
+    case SB2_ESCRATCH:
+      return "problem needs more scratch memory than the static buffer of sb2_collision_noalloc "
+             "(SB2_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }
@@ -1312,6 +1316,79 @@ int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_
   if (!v || !h || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
   const CollPlan c = coll_plan(N, T, prec);
   if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
+  {
+    StageTimer tm(5, s);
+    SB2_TRY(propagators(N, T, h, dt, U, reinterpret_cast<cplx*>(at(ws, c.ex1)),
+                        reinterpret_cast<cplx*>(at(ws, c.ex2)), s));
+  }
+  SB2_TRY(collision_core(N, T, v, U, rho_hist, dt, reinterpret_cast<cplx*>(I_out),
+                         reinterpret_cast<cplx*>(Sigma_out), prec, c, ws, s));
+  return SB2_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of sb2_collision: its scratch memory is a static
+// device array of SB2_NOALLOC_SCRATCH_BYTES bytes (each device that runs the
+// library holds its own copy until the process ends).  In host code the
+// array's name is only a stand-in for its device address: the address is read
+// once per device with hipGetSymbolAddress, with that device current, and only
+// that pointer is handed to kernels.  The chunk of past times one pass of the
+// contraction chain holds is the largest whose workspace fits the array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SB2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device (looked up on first use)
+hipError_t scratch_ptr(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// largest chunk of past times whose collision workspace fits `cap` bytes (0: none)
+int noalloc_chunk(int N, int T, int prec, size_t cap) {
+  int hi = coll_plan(N, T, prec).ch.S;
+  if (coll_plan(N, T, prec, 1).end > cap) return 0;
+  int lo = 1;                                  // fits
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (coll_plan(N, T, prec, mid).end <= cap) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+}  // namespace
+
+extern "C" {
+
+int sb2_collision_noalloc(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
+                          void* I_out, void* Sigma_out, int prec, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !I_out || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  const int S = noalloc_chunk(N, T, prec, SB2_NOALLOC_SCRATCH_BYTES);
+  if (S < 1) return SB2_ESCRATCH;
+  const CollPlan c = coll_plan(N, T, prec, S);
+  void* ws = nullptr;
+  SB2_TRY(scratch_ptr(&ws));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
   {

@@ -117,3 +117,14 @@ def test_autotune_arguments_and_tuning_table(L):
     for p in (0, 1, 2):
         assert s(23, p, 768, 100, 512) == 0      # back to the defaults
     assert before == after
+
+
+def test_noalloc_entry_rejects_before_touching_the_device(L):
+    c = L.sb2_collision_noalloc
+    assert c(0, 10, FAKE, FAKE, FAKE, 0.05, FAKE, None, 0, None) == -2
+    assert c(10, 10, None, FAKE, FAKE, 0.05, FAKE, None, 0, None) == -1
+    assert c(10, 10, FAKE, FAKE, FAKE, -1.0, FAKE, None, 0, None) == -1
+    # larger than the static scratch buffer (even one past time per pass)
+    for n, prec in ((128, 2), (64, 1), (48, 0)):
+        assert c(n, 100, FAKE, FAKE, FAKE, 0.05, FAKE, None, prec, None) == -6
+    assert b"static buffer" in L.sb2_status_string(-6)
