@@ -55,8 +55,20 @@ def rel_f(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sys_, nsample: int):
-    """FP64 oracle on `nsample` past times, scaled to one full step (T past times)."""
+    """FP64 oracle on `nsample` past times, scaled to one full step (T past times).
+    `cores` is the number of BLAS threads the oracle's products ran on."""
     from oracle import sb2_oracle as o
     try:
         from threadpoolctl import threadpool_info
@@ -77,7 +89,86 @@ def cpu_baseline(sys_, nsample: int):
     return {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{len(ks)} of {t_len} past times (Sigma^<, Sigma^>, collision term each) at N={n}, "
                       f"{dt_s:.1f} s, scaled by T/{len(ks)} (cost is linear in T)",
-            "seconds_per_step": per_step}
+            "seconds_per_step": per_step, "cpu": cpu_model(), "threads": int(cores),
+            "host_cpus": os.cpu_count()}
+
+
+def eq4_error(torch, _lib, dev, prec, n, t, nk=3):
+    """Error of the path on an interaction with exactly the 8-fold symmetry of
+    Eq. 4 (Coulomb-like integrals of real orbitals), where the exchange term is
+    not a multiple of the direct one: sampled Sigma^<, Sigma^> against the
+    oracle at nk past times (the full I would need the oracle over all T)."""
+    from oracle import sb2_oracle as o
+    from paper_1905_01180_amd import inputs as gen
+    s = gen.make_system(n, t, config_id=2, system_id=1, v_kind="orbitals")
+    got, sig = _lib.sb2_collision(torch.from_numpy(s.v).to(dev), torch.from_numpy(s.h).to(dev),
+                                  torch.from_numpy(s.rho_hist).to(dev), s.dt, prec, return_sigma=True)
+    ks = sorted({0, t // 2, t - 1})[:nk]
+    sig = sig[:, torch.as_tensor(ks, device=dev)].cpu().numpy()
+    w = o.exchange_combined(s.v)
+    zero = np.zeros((n, n), np.complex128)
+    worst = 0.0
+    for i, k in enumerate(ks):
+        u = o.propagator(s.h, (t - k) * s.dt)
+        gl, gg, glb, ggb = o.gkba_pair(u, s.rho_hist[k], zero)
+        worst = max(worst, rel_f(sig[0, i], o.sigma(s.v, gl, ggb, w)), rel_f(sig[1, i], o.sigma(s.v, gg, glb, w)))
+    return {"v": "real-orbital Coulomb-like integrals (8-fold symmetry of Eq. 4)", "sigma_rel_F_max": worst,
+            "sigma_ks": ks}
+
+
+def legs(torch, _lib, gen, dev, prec):
+    """Short measurements of the other workloads, reported beside the headline:
+    config 1 (N=50, T=500, float64) against its stored oracle values, config 3
+    (N=64, T=256: forward and hand-written adjoint, float64) and config 4 (32
+    systems, N 24..96, T 64..512: one batched call against 32 single calls)."""
+    out = {}
+
+    def tsec(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    # config 1: float64 baseline
+    s = gen.make_config(1)
+    v, h, r = (torch.from_numpy(x).to(dev) for x in (s.v, s.h, s.rho_hist))
+    sec = tsec(lambda: _lib.sb2_collision(v, h, r, s.dt, "fp64"), 3)
+    c1 = {"workload": "N=50, T=500, float64", "steps_per_s": 1.0 / sec,
+          "tflops_algorithmic": 48.0 * s.t * s.n ** 5 / sec / 1e12,
+          "frac_fp64_peak": 48.0 * s.t * s.n ** 5 / sec / 1e12 / PEAK_TFLOPS["fp64"]}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_c1.npz")
+    if os.path.exists(gold):
+        z = np.load(gold)
+        c1["I_rel_F"] = rel_f(_lib.sb2_collision(v, h, r, s.dt, "fp64").cpu().numpy(), z["i_ns"])
+    out["c1_fp64"] = c1
+    del v, h, r
+    # config 3: forward + adjoint
+    s = gen.make_config(3)
+    v, h, r = (torch.from_numpy(x).to(dev) for x in (s.v, s.h, s.rho_hist))
+    gi = (1j * h.conj().T).contiguous()          # dL/dI for L = Im tr[h I] in torch's convention
+    t_f = tsec(lambda: _lib.sb2_collision(v, h, r, s.dt, "fp64"), 2)
+    t_b = tsec(lambda: _lib.sb2_collision_backward(v, h, r, s.dt, gi), 2)
+    n5 = float(s.n) ** 5
+    out["c3_adjoint_fp64"] = {
+        "workload": "N=64, T=256, float64, L = Im tr[h I]", "forward_s": t_f, "backward_s": t_b,
+        "backward_over_forward": t_b / t_f,
+        # backward: forward chain recomputed (24 N^5 per self-energy) + eight adjoint contractions (48 N^5)
+        "backward_tflops_algorithmic": 2 * s.t * 72.0 * n5 / t_b / 1e12,
+        "backward_frac_fp64_peak": 2 * s.t * 72.0 * n5 / t_b / 1e12 / PEAK_TFLOPS["fp64"]}
+    del v, h, r
+    # config 4: batched against single calls (eager)
+    systems = gen.make_batch(32, config_id=4)
+    data = [tuple(torch.from_numpy(x).to(dev) for x in (q.v, q.h, q.rho_hist)) + (q.dt,) for q in systems]
+    t_seq = tsec(lambda: [_lib.sb2_collision(a, b, c, d, prec) for (a, b, c, d) in data], 1)
+    t_grp = tsec(lambda: _lib.sb2_collision_batched(data, prec), 1)
+    flops = sum(48.0 * q.t * float(q.n) ** 5 for q in systems)
+    out["c4_batched"] = {"workload": "32 systems, N ~ U{24..96}, T ~ U{64..512}, " + prec,
+                         "batched_s": t_grp, "sequential_s": t_seq, "speedup": t_seq / t_grp,
+                         "tflops_algorithmic": flops / t_grp / 1e12}
+    return out
 
 
 def main():
@@ -90,7 +181,9 @@ def main():
     ap.add_argument("--t", type=int, default=1000)
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other precisions")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=12)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the short measurements of the other workloads (N=50 FP64, adjoint, batched)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (calibration point for hardware byte counters)")
     ap.add_argument("--no-error", action="store_true", help="skip the accuracy check against the stored oracle")
@@ -207,7 +300,10 @@ def main():
                 traffic = tj.get("bytes_per_launch")
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic, "kernel": dom, "launch_ms": per_launch_ms,
-                "flops_per_launch": flops_per_launch}
+                "flops_per_launch": flops_per_launch,
+                "traffic_source": (os.path.relpath(tf, ROOT) + ": rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of a "
+                                   "separate run, calibrated by a device copy; valid for the kernel sources' hash")
+                if traffic is not None else "no counter run for the current kernel sources"}
         if args.prec == "fp16x3":
             roof["note"] = ("algorithmic flops vs the dense fp16 peak; each real product costs three fp16 "
                             "MFMAs, so the split method's ceiling is frac = 1/3")
@@ -227,6 +323,9 @@ def main():
                "sigma_ks": [int(k) for k in ks],
                "kappa_I": float(z["term_norms"].sum() / np.linalg.norm(z["i_ns"]))}
         del sig
+        if (args.n, args.t) == (100, 1000):
+            log("error on a real-orbital interaction (Eq. 4 symmetry)")
+            err["eq4_interaction"] = eq4_error(torch, _lib, dev, args.prec, args.n, args.t)
 
     compare = {}
     if not args.no_compare:
@@ -237,6 +336,11 @@ def main():
             log(f"timing {p} for comparison")
             e2, _ = timed(p, 1, 1, False)
             compare[p] = 1.0 / e2
+
+    other = None
+    if not args.no_legs and (args.n, args.t) == (100, 1000):
+        log("other workloads: N=50 FP64, adjoint N=64 T=256, 32-system batch")
+        other = legs(torch, _lib, gen, dev, args.prec)
 
     cpu = None
     if not args.no_cpu:
@@ -251,7 +355,7 @@ def main():
                    "N": args.n, "T": args.t, "prec": args.prec},
         "tflops_algorithmic": flops_step * value / 1e12,
         "roofline": roof, "cpu_baseline": cpu, "rel_err": err, "steps_per_s_by_prec": compare or None,
-        "stages": stages, "kernel_hash": kernel_hash(), "tuning": tuned,
+        "stages": stages, "kernel_hash": kernel_hash(), "tuning": tuned, "other_workloads": other,
     }
     print(json.dumps(out), flush=True)
 

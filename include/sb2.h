@@ -22,10 +22,19 @@
  *    rho_hist[k] = rho(t_k), the one-particle density matrix -i G^<(t_k, t_k).
  *  * Return value: SB2_OK or a negative sb2_status.  Argument errors are
  *    detected on the host before anything is enqueued (outputs untouched).
- *    A HIP launch failure returns SB2_EHIP; asynchronous device faults surface
- *    through the HIP runtime on the caller's next synchronisation.
+ *    A HIP launch failure returns SB2_EHIP.  An error that an earlier
+ *    asynchronous failure left in the HIP runtime (of this library's work or
+ *    any other) is returned as SB2_EHIP by the next call that would enqueue
+ *    work, and cleared; device faults also surface through the HIP runtime on
+ *    the caller's next synchronisation.
  *  * Inputs are assumed Hermitian where the physics says so (h, rho_k); NaN or
- *    Inf inputs propagate to the outputs.
+ *    Inf inputs propagate to the outputs.  With the environment variable
+ *    SB2_CHECK=1 every entry point that enqueues work first checks its inputs
+ *    on the device (all values finite; h and every rho_k Hermitian to 1e-10
+ *    relative to max(1, max |entry|)) and returns SB2_ECHECK, with nothing
+ *    else enqueued, if one fails.  The check synchronises the stream (it
+ *    copies three words to the host), so it is for debugging, not for timed
+ *    runs or stream capture.
  *  * prec selects the arithmetic of the bulk tensor contractions only.  The
  *    propagators, GKBA two-time functions, the sum over past times and every
  *    output stay float64:
@@ -34,7 +43,12 @@
  *                      folded into float64 along the long contraction,
  *      SB2_SPLIT_FP16  each float32 operand split into two scaled float16 pieces,
  *                      three float16 products per real product (hi*hi + hi*lo +
- *                      lo*hi) with float32 accumulation on the FP16 matrix cores.
+ *                      lo*hi) with float32 accumulation on the FP16 matrix cores,
+ *      SB2_SPLIT_BF16  not built (SB2_EUNSUPPORTED): two bfloat16 pieces carry
+ *                      16 significant bits (about 1e-5, short of the 1e-6 target)
+ *                      and three pieces need six products per real product at
+ *                      the FP16 rate, twice the cost of SB2_SPLIT_FP16 for the
+ *                      same accuracy.
  *  * Calls that share a workspace must be ordered on one stream.
  */
 #ifndef SB2_H
@@ -53,14 +67,16 @@ typedef enum {
   SB2_EWORKSPACE = -3,   /* ws_bytes smaller than sb2_workspace_size(...)           */
   SB2_EHIP = -4,         /* a HIP runtime call or kernel launch failed              */
   SB2_EUNSUPPORTED = -5, /* precision not available for this entry point            */
-  SB2_ESCRATCH = -6      /* sb2_collision_noalloc: problem too large for its static
+  SB2_ESCRATCH = -6,     /* sb2_collision_noalloc: problem too large for its static
                             scratch buffer                                          */
+  SB2_ECHECK = -7        /* SB2_CHECK=1 input check failed                          */
 } sb2_status;
 
 typedef enum {
   SB2_FP64 = 0,
   SB2_FP32 = 1,
-  SB2_SPLIT_FP16 = 2
+  SB2_SPLIT_FP16 = 2,
+  SB2_SPLIT_BF16 = 3     /* recognised, not built: every entry point returns SB2_EUNSUPPORTED */
 } sb2_precision;
 
 /* Operation codes for sb2_workspace_size. */

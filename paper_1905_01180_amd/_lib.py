@@ -18,13 +18,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsb2.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2, "bf16x6": 3}   # bf16x6: recognised, not built
 OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4, "propagate": 5,
        "collision_diagonal": 6, "collision_symmetric": 7}
 VERTICES = {"diagonal": 1, "symmetric": 2}
 PROP_HF, PROP_COLLISION = 1, 2
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
-          -5: "SB2_EUNSUPPORTED", -6: "SB2_ESCRATCH"}
+          -5: "SB2_EUNSUPPORTED", -6: "SB2_ESCRATCH",
+          -7: "SB2_ECHECK"}
 
 _lib = None
 _lock = threading.Lock()

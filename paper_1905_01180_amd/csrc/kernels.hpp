@@ -32,6 +32,31 @@ __global__ void k_fill_u32(unsigned* p, int n, unsigned val) {
   if (i < n) p[i] = val;
 }
 
+// Optional input checks (SB2_CHECK=1).  out[0] is raised to max |X_ij -
+// conj(X_ji)| over the nmat N x N matrices, out[1] to max |X_ij| (float bits of
+// non-negative values), out[2] is set when any entry is not finite.
+__global__ void k_check_herm(int N, i64 nmat, const cplx* __restrict__ X, unsigned* out) {
+  const i64 nn = (i64)N * N;
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nmat * nn) return;
+  const i64 m = idx / nn;
+  const int i = (int)((idx - m * nn) / N), j = (int)(idx - m * nn - (i64)i * N);
+  const cplx a = X[idx], b = X[m * nn + (i64)j * N + i];
+  if (!isfinite(a[0]) || !isfinite(a[1])) {
+    atomicOr(out + 2, 1u);
+    return;
+  }
+  const double d = fmax(fabs(a[0] - b[0]), fabs(a[1] + b[1]));
+  const double x = fmax(fabs(a[0]), fabs(a[1]));
+  if (d > 0.0) atomicMax(out, __float_as_uint((float)d));
+  if (x > 0.0) atomicMax(out + 1, __float_as_uint((float)x));
+}
+
+__global__ void k_check_finite(i64 n, const double* __restrict__ x, unsigned* out) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n && !isfinite(x[idx])) atomicOr(out + 2, 1u);
+}
+
 // Block-wide max, then one atomic per block.
 __device__ __forceinline__ void block_atomic_max(float x, unsigned* dst) {
   __shared__ float red[16];

@@ -16,9 +16,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <algorithm>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -39,6 +41,8 @@ constexpr size_t INTERMEDIATE_BUDGET = 32ull << 30;  // bytes for the two chain 
 
 
 inline bool prec_ok(int p) { return p == SB2_FP64 || p == SB2_FP32 || p == SB2_SPLIT_FP16; }
+// SB2_SPLIT_BF16 is a known precision that no entry point implements
+inline int prec_status(int p) { return prec_ok(p) ? SB2_OK : (p == SB2_SPLIT_BF16 ? SB2_EUNSUPPORTED : SB2_EINVAL); }
 inline size_t bulk_bytes(int p) { return p == SB2_FP64 ? 8 : 4; }   // one real scalar of the bulk type
 
 GemmArgs gdef() {
@@ -346,6 +350,72 @@ struct StageTimer {
   } while (0)
 
 inline int blocks(long long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+#define SB2_PREC(p)                          \
+  do {                                       \
+    const int ps_ = prec_status(p);          \
+    if (ps_ != SB2_OK) return ps_;           \
+  } while (0)
+
+// An error left by an earlier asynchronous failure is reported (and cleared)
+// by the next entry point that enqueues work.
+#define SB2_ENTRY()                                         \
+  do {                                                      \
+    if (hipGetLastError() != hipSuccess) return SB2_EHIP;   \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Optional input checks, run when the environment has SB2_CHECK=1: every
+// input finite, h and the density matrices Hermitian to 1e-10 relative.  They
+// synchronise the stream (a device-to-host copy of three words at `scr`, the
+// start of the call's scratch memory, before any work is enqueued), so they
+// are off the hot path and not for use under stream capture.
+// ---------------------------------------------------------------------------
+bool check_on() {
+  const char* e = std::getenv("SB2_CHECK");
+  return e && e[0] == '1' && e[1] == 0;
+}
+
+struct CheckItem {
+  int kind;          // 0: N x N complex matrices that must be Hermitian, 1: finite complex, 2: finite real
+  const void* p;
+  i64 count;         // matrices (kind 0) or scalars (kinds 1, 2)
+};
+
+int run_checks(hipStream_t s, void* scr, int N, std::initializer_list<CheckItem> items) {
+  unsigned* out = reinterpret_cast<unsigned*>(scr);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, out, 3, 0u);
+  for (const CheckItem& it : items) {
+    if (!it.p || it.count < 1) continue;
+    if (it.kind == 0) {
+      const i64 n = it.count * N * N;
+      hipLaunchKernelGGL(k_check_herm, dim3(blocks(n, 256)), dim3(256), 0, s, N, it.count,
+                         reinterpret_cast<const cplx*>(it.p), out);
+    } else {
+      const i64 n = it.kind == 1 ? 2 * it.count : it.count;
+      hipLaunchKernelGGL(k_check_finite, dim3(blocks(n, 256)), dim3(256), 0, s, n,
+                         reinterpret_cast<const double*>(it.p), out);
+    }
+    if (hipGetLastError() != hipSuccess) return SB2_EHIP;
+  }
+  unsigned host[3] = {0, 0, 0};
+  if (hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s) != hipSuccess) return SB2_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return SB2_EHIP;
+  float herm, mx;
+  std::memcpy(&herm, &host[0], 4);
+  std::memcpy(&mx, &host[1], 4);
+  if (host[2] != 0) return SB2_ECHECK;
+  if ((double)herm > 1e-10 * std::max(1.0, (double)mx)) return SB2_ECHECK;
+  return SB2_OK;
+}
+
+#define SB2_CHECKS(scr, N, ...)                                               \
+  do {                                                                        \
+    if (check_on()) {                                                         \
+      const int cs_ = run_checks(reinterpret_cast<hipStream_t>(stream), (scr), (N), {__VA_ARGS__}); \
+      if (cs_ != SB2_OK) return cs_;                                          \
+    }                                                                         \
+  } while (0)
 
 // ---------------------------------------------------------------------------
 // The chain for one chunk of ns slices
@@ -1199,7 +1269,9 @@ const char* sb2_status_string(int status) {
     case SB2_ESHAPE: return "size out of range (N, T or batch count)";
     case SB2_EWORKSPACE: return "workspace smaller than sb2_workspace_size()";
     case SB2_EHIP: return "HIP runtime error while enqueueing work";
-    case SB2_EUNSUPPORTED: return "precision not supported by this entry point";
+    case SB2_EUNSUPPORTED: return "precision not supported by this entry point (SB2_SPLIT_BF16 is not built)";
+    case SB2_ECHECK:
+      return "input check failed (SB2_CHECK=1): a non-finite input, or h or a density matrix not Hermitian";
     case SB2_ESCRATCH:
       return "problem needs more scratch memory than the static buffer of sb2_collision_noalloc "
              "(SB2_NOALLOC_SCRATCH_BYTES)";
@@ -1241,9 +1313,12 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
 int sb2_sigma(int N, int B, const double* v, const void* Gl, const void* Gg, void* Sl, void* Sg, int prec,
               void* ws, size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || B < 1) return SB2_ESHAPE;
-  if (!v || !Gl || !Gg || !Sl || !Sg || !ws || !prec_ok(prec)) return SB2_EINVAL;
+  if (!v || !Gl || !Gg || !Sl || !Sg || !ws) return SB2_EINVAL;
+  SB2_PREC(prec);
   const ChainPlan p = chain_plan(N, B, prec, 0);
   if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {1, Gl, (i64)B * N * N}, {1, Gg, (i64)B * N * N});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = sigma_pairs(prec, N, B, v, Gl, Gg, nullptr, nullptr, 1, reinterpret_cast<cplx*>(Sl),
                              reinterpret_cast<cplx*>(Sg), nullptr, nullptr, p, ws, s);
@@ -1313,9 +1388,12 @@ hipError_t collision_core(int N, int T, const double* v, const cplx* U, const vo
 int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, void* I_out,
                   void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
-  if (!v || !h || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  if (!v || !h || !rho_hist || !I_out || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  SB2_PREC(prec);
   const CollPlan c = coll_plan(N, T, prec);
   if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, T});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
   {
@@ -1383,12 +1461,15 @@ extern "C" {
 int sb2_collision_noalloc(int N, int T, const double* v, const void* h, const void* rho_hist, double dt,
                           void* I_out, void* Sigma_out, int prec, void* stream) {
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
-  if (!v || !h || !rho_hist || !I_out || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  if (!v || !h || !rho_hist || !I_out || !finite_pos(dt)) return SB2_EINVAL;
+  SB2_PREC(prec);
   const int S = noalloc_chunk(N, T, prec, SB2_NOALLOC_SCRATCH_BYTES);
   if (S < 1) return SB2_ESCRATCH;
   const CollPlan c = coll_plan(N, T, prec, S);
+  SB2_ENTRY();
   void* ws = nullptr;
   SB2_TRY(scratch_ptr(&ws));
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, T});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
   {
@@ -1404,9 +1485,12 @@ int sb2_collision_noalloc(int N, int T, const double* v, const void* h, const vo
 int sb2_collision_prop(int N, int T, const double* v, const void* U_hist, const void* rho_hist, double dt,
                        void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
-  if (!v || !U_hist || !rho_hist || !I_out || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  if (!v || !U_hist || !rho_hist || !I_out || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  SB2_PREC(prec);
   const CollPlan c = coll_plan(N, T, prec);
   if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {1, U_hist, (i64)T * N * N}, {0, rho_hist, T});
   SB2_TRY(collision_core(N, T, v, reinterpret_cast<const cplx*>(U_hist), rho_hist, dt,
                          reinterpret_cast<cplx*>(I_out), reinterpret_cast<cplx*>(Sigma_out), prec, c, ws,
                          reinterpret_cast<hipStream_t>(stream)));
@@ -1465,6 +1549,8 @@ int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const v
   if (vertex != SB2_VERTEX_DIAGONAL && vertex != SB2_VERTEX_SYMMETRIC) return SB2_EINVAL;
   const VertPlan p = vert_plan(N, T, vertex);
   if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, vparam, vertex == SB2_VERTEX_DIAGONAL ? (i64)N : (i64)N * N}, {0, h, 1}, {0, rho_hist, T});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const i64 nn = (i64)N * N;
   auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
@@ -1515,11 +1601,14 @@ int sb2_v8_expand(int N, const double* packed, double* v, void* stream) {
 int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
                        void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
-  if (!v || !h || !rho_hist || !U_hist || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  if (!v || !h || !rho_hist || !U_hist || !ws || !finite_pos(dt)) return SB2_EINVAL;
   if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
+  SB2_PREC(prec);
   const int n_end = n0 + nsteps;
   const PropPlan p = prop_plan(N, n_end, prec);
   if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, U_hist, (i64)n0 * N * N});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const i64 nn = (i64)N * N;
   const size_t mb = (size_t)nn * C128;
@@ -1586,6 +1675,8 @@ int sb2_rho_step(int N, const void* h, const void* rho, const void* I, double dt
   if (N < 1 || N > SB2_MAX_N) return SB2_ESHAPE;
   if (!h || !rho || !I || !rho_out || !ws || !finite_pos(dt)) return SB2_EINVAL;
   if (ws_bytes < rho_plan(N)) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {0, h, 1}, {0, rho, 1}, {1, I, (i64)N * N});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t m = al((size_t)N * N * C128);
   cplx* U = reinterpret_cast<cplx*>(at(ws, 0));
@@ -1618,10 +1709,12 @@ int sb2_collision_backward(int N, int T, const double* v, const void* h, const v
                            size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
   if (!v || !h || !rho_hist || !gI || !gv || !gh || !grho || !ws || !finite_pos(dt)) return SB2_EINVAL;
-  if (!prec_ok(prec)) return SB2_EINVAL;
+  SB2_PREC(prec);
   if (prec != SB2_FP64) return SB2_EUNSUPPORTED;
   const BwdPlan b = bwd_plan(N, T);
   if (ws_bytes < b.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, T}, {1, gI, (i64)N * N});
   hipError_t e = collision_backward(N, T, v, h, rho_hist, dt, gI, gv, gh, grho, b, ws,
                                     reinterpret_cast<hipStream_t>(stream));
   return e == hipSuccess ? SB2_OK : SB2_EHIP;
@@ -1630,7 +1723,8 @@ int sb2_collision_backward(int N, int T, const double* v, const void* h, const v
 int sb2_autotune(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, int prec, void* ws,
                  size_t ws_bytes, void* stream, int* persist_out, int* r4pct_out, int* fused_out) {
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
-  if (!v || !h || !rho_hist || !ws || !prec_ok(prec) || !finite_pos(dt)) return SB2_EINVAL;
+  if (!v || !h || !rho_hist || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  SB2_PREC(prec);
   const int Tt = tune_len(N, T, prec);
   const size_t need = tune_bytes(N, T, prec);
   if (ws_bytes < need) return SB2_EWORKSPACE;
@@ -1699,7 +1793,8 @@ int sb2_autotune(int N, int T, const double* v, const void* h, const void* rho_h
 }
 
 int sb2_set_tuning(int N, int prec, int persist, int r4pct, int fused_wgs) {
-  if (N < 1 || N > SB2_MAX_N || !prec_ok(prec)) return SB2_EINVAL;
+  if (N < 1 || N > SB2_MAX_N) return SB2_EINVAL;
+  SB2_PREC(prec);
   if (persist < 1 || r4pct < 10 || r4pct > 200 || fused_wgs < 0) return SB2_EINVAL;
   TuneCfg tc;
   tc.persist = persist;
@@ -1721,13 +1816,14 @@ size_t sb2_batched_workspace_size(int nsys, const sb2_system* sys, int prec) {
 }
 
 int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, size_t ws_bytes, void* stream) {
-  if (nsys < 1 || !sys || !ws || !prec_ok(prec)) return SB2_EINVAL;
+  if (nsys < 1 || !sys || !ws) return SB2_EINVAL;
   if (nsys > MAX_GROUP) return SB2_ESHAPE;
   for (int b = 0; b < nsys; ++b) {
     const sb2_system& q = sys[b];
     if (q.N < 1 || q.N > SB2_MAX_N || q.T < 1 || q.T > SB2_MAX_T) return SB2_ESHAPE;
     if (!q.v || !q.h || !q.rho_hist || !q.I_out || !finite_pos(q.dt)) return SB2_EINVAL;
   }
+  SB2_PREC(prec);
   // systems of one 16-wide bucket of N share the rounds (and the whole
   // intermediate budget); the buckets, then the solo systems, run one after
   // the other in one enqueue
@@ -1739,6 +1835,11 @@ int sb2_collision_batched(int nsys, const sb2_system* sys, int prec, void* ws, s
   }
   for (int b = 0; b < nsys; ++b)
     if (batch_solo(sys[b]) && ws_bytes < coll_plan(sys[b].N, sys[b].T, prec).end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  for (int b = 0; b < nsys; ++b) {
+    const sb2_system& q = sys[b];
+    SB2_CHECKS(ws, q.N, {2, q.v, (i64)q.N * q.N * q.N * q.N}, {0, q.h, 1}, {0, q.rho_hist, q.T});
+  }
   for (size_t i = 0; i < buckets.size(); ++i) {
     const hipError_t e = collision_batched((int)buckets[i].size(), buckets[i].data(), prec, plans[i], ws,
                                            reinterpret_cast<hipStream_t>(stream));

@@ -128,3 +128,28 @@ def test_noalloc_entry_rejects_before_touching_the_device(L):
     for n, prec in ((128, 2), (64, 1), (48, 0)):
         assert c(n, 100, FAKE, FAKE, FAKE, 0.05, FAKE, None, prec, None) == -6
     assert b"static buffer" in L.sb2_status_string(-6)
+
+
+def test_split_bf16_is_recognised_but_not_built(L):
+    big = 1 << 40
+    bf16 = 3
+    assert L.sb2_sigma(10, 2, FAKE, FAKE, FAKE, FAKE, FAKE, bf16, FAKE, big, None) == -5
+    assert L.sb2_collision(10, 10, FAKE, FAKE, FAKE, 0.05, FAKE, None, bf16, FAKE, big, None) == -5
+    assert L.sb2_collision_noalloc(10, 10, FAKE, FAKE, FAKE, 0.05, FAKE, None, bf16, None) == -5
+    assert L.sb2_collision_prop(10, 10, FAKE, FAKE, FAKE, 0.05, FAKE, None, bf16, FAKE, big, None) == -5
+    assert L.sb2_collision_backward(10, 10, FAKE, FAKE, FAKE, 0.05, FAKE, FAKE, FAKE, FAKE, bf16, FAKE, big,
+                                    None) == -5
+    assert L.sb2_gkba_propagate(10, 0, 1, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, bf16, FAKE, big, None) == -5
+    assert L.sb2_autotune(10, 10, FAKE, FAKE, FAKE, 0.05, bf16, FAKE, big, None, None, None, None) == -5
+    assert L.sb2_set_tuning(10, bf16, 768, 100, 512) == -5
+    arr = (_lib.SystemDesc * 1)()
+    arr[0].N, arr[0].T, arr[0].dt = 10, 10, 0.05
+    arr[0].v = arr[0].h = arr[0].rho_hist = arr[0].I_out = FAKE
+    assert L.sb2_collision_batched(1, arr, bf16, FAKE, big, None) == -5
+    assert L.sb2_batched_workspace_size(1, arr, bf16) == 0
+    for op in range(8):
+        assert _lib.sb2_workspace_size(op, 10, 10, bf16) == 0
+    # an unknown precision stays an invalid argument
+    assert L.sb2_collision(10, 10, FAKE, FAKE, FAKE, 0.05, FAKE, None, 4, FAKE, big, None) == -1
+    assert b"BF16" in L.sb2_status_string(-5)
+    assert b"SB2_CHECK" in L.sb2_status_string(-7)
