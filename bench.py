@@ -194,6 +194,11 @@ def main():
                     help="time whole GKBA propagation steps (HF + second-Born collisions) from a history of --t steps")
     ap.add_argument("--vertex", choices=["diagonal", "symmetric"],
                     help="time the special-vertex collision integral (float64) at --n, --t")
+    ap.add_argument("--chain", choices=["hubbard", "ohno"],
+                    help="the paper's chain propagations of Sec. IV (N_b=10, J=-1, U=1; hubbard: diagonal "
+                         "vertex, 5000 steps of 0.01; ohno: symmetric vertex, 2000 steps of 0.025), float64")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the forward and the hand-written adjoint (float64) at --n, --t (default N=64, T=256)")
     ap.add_argument("--small-batch", action="store_true",
                     help="with --batched: 32 small systems (N 8..24, T 16..64) instead of N 24..96, T 64..512")
     args = ap.parse_args()
@@ -221,6 +226,10 @@ def main():
         return propagate(args, torch, _lib, gen, dev)
     if args.vertex:
         return vertex(args, torch, _lib, gen, dev)
+    if args.adjoint:
+        return adjoint(args, torch, _lib, gen, dev)
+    if args.chain:
+        return chain(args, torch, _lib, gen, dev)
 
     cid = 2 if (args.n, args.t) == (100, 1000) else 99
     log(f"generating inputs N={args.n} T={args.t}")
@@ -506,6 +515,95 @@ def vertex(args, torch, _lib, gen, dev):
         "config": {"workload": "GKBA collision integral, %s-basis vertex, N=%d, T=%d, dt=%g" % (args.vertex, n, t, s.dt),
                    "N": n, "T": t},
         "tflops_algorithmic": (common + sig_flops) / sec / 1e12, "roofline": roof, "stage_ms": stages,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def adjoint(args, torch, _lib, gen, dev):
+    """Forward and hand-written adjoint of the collision integral (float64) for
+    the scalar L = Im tr[h I] (config 3: N=64, T=256 unless --n/--t are given).
+    value = backward passes/s; algorithmic flops of the backward: the forward
+    chain recomputed (24 N^5 per self-energy) and the eight adjoint
+    contractions (48 N^5 per self-energy), against the FP64 matrix-core peak."""
+    n, t = (64, 256) if (args.n, args.t) == (100, 1000) else (args.n, args.t)
+    s = gen.make_config(3) if (n, t) == (64, 256) else gen.make_system(n, t, config_id=99)
+    v, h, r = (torch.from_numpy(x).to(dev) for x in (s.v, s.h, s.rho_hist))
+    gi = (1j * h.conj().T).contiguous()          # dL/dI for L = Im tr[h I] (torch convention)
+
+    def tsec(fn, reps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    log(f"adjoint: N={n} T={t}")
+    t_f = tsec(lambda: _lib.sb2_collision(v, h, r, s.dt, "fp64"), args.steps, args.warmup)
+    t_b = tsec(lambda: _lib.sb2_collision_backward(v, h, r, s.dt, gi), args.steps, args.warmup)
+    n5 = float(n) ** 5
+    fl_b = 2 * t * 72.0 * n5
+    ach = fl_b / t_b / 1e12
+    out = {
+        "metric": "collision-integral adjoint passes/s (N=%d, T=%d, float64)" % (n, t),
+        "value": 1.0 / t_b, "unit": "backward/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint of the GKBA collision integral, L = Im tr[h I], N=%d, T=%d" % (n, t),
+                   "N": n, "T": t},
+        "forward_ms": 1e3 * t_f, "backward_over_forward": t_b / t_f,
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": ach / PEAK_TFLOPS["fp64"], "traffic": None, "kernel": "whole backward pass"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+# the paper's single-core runtimes of these runs (Table I): loop, contraction (s)
+PAPER_CHAIN_S = {"hubbard": (177.0, 164.0), "ohno": (1213.0, 731.0)}
+
+
+def chain(args, torch, _lib, gen, dev):
+    """The chain propagations of Sec. IV on the device: N_b = 10 sites, hopping
+    J = -1, on-site U = 1 (Hubbard, diagonal vertex: 5000 steps of 0.01) or
+    the Ohno interaction V_ij = U / sqrt(1 + |i - j|^2) (symmetric vertex:
+    2000 steps of 0.025), starting with the left half filled (the state a
+    strong confinement gives), HF + second-Born collisions, float64.  The
+    whole run is one library call; value = time steps per second."""
+    n = 10
+    vertex, steps, dt = ("diagonal", 5000, 0.01) if args.chain == "hubbard" else ("symmetric", 2000, 0.025)
+    h = torch.from_numpy(gen.chain_hopping(n, -1.0)).to(dev)
+    par = gen.hubbard_onsite(n, 1.0) if vertex == "diagonal" else gen.ohno_matrix(n, 1.0)
+    par = torch.from_numpy(par).to(dev)
+    rho = torch.zeros((steps + 1, n, n), dtype=torch.complex128, device=dev)
+    u = torch.zeros((steps, n, n), dtype=torch.complex128, device=dev)
+    rho[0].copy_(torch.from_numpy(gen.left_half_density(n)))
+    log(f"chain {args.chain}: {steps} steps of {dt}")
+    # warm-up: a short run on scratch copies (library load, kernel code objects)
+    r2, u2 = rho[:11].clone(), u[:10].clone()
+    _lib.sb2_gkba_propagate_vertex(vertex, par, h, r2, u2, 0, 10, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _lib.sb2_gkba_propagate_vertex(vertex, par, h, rho, u, 0, steps, dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    occ = torch.diagonal(rho, dim1=1, dim2=2).real.cpu().numpy()
+    tr = occ.sum(axis=1)
+    every = steps // 10
+    loop_s, contr_s = PAPER_CHAIN_S[args.chain]
+    out = {
+        "metric": "GKBA chain propagation steps/s (Sec. IV, N_b=10, %s vertex, %d steps of %g)" % (vertex, steps, dt),
+        "value": steps / wall, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": 1e3 * wall / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%s chain, N_b=10, J=-1, U=1, left half filled at t=0, HF + 2B, %d x %g" %
+                               (args.chain, steps, dt), "N": n, "steps": steps, "dt": dt},
+        "wall_s": wall, "trace_drift": float(np.abs(tr - tr[0]).max() / tr[0]),
+        "left_half_occupation": {f"t={m * dt:g}": float(occ[m, : n // 2].sum()) for m in range(0, steps + 1, every)},
+        "site_occupation_final": [float(x) for x in occ[-1]],
+        "paper_single_core_s": {"loop": loop_s, "contraction": contr_s,
+                                "hardware": "Intel Core i5-4460, 1 core (context, other machine)"},
     }
     print(json.dumps(out), flush=True)
 

@@ -88,7 +88,9 @@ typedef enum {
   SB2_OP_AUTOTUNE = 4,
   SB2_OP_PROPAGATE = 5,
   SB2_OP_COLLISION_DIAGONAL = 6,
-  SB2_OP_COLLISION_SYMMETRIC = 7
+  SB2_OP_COLLISION_SYMMETRIC = 7,
+  SB2_OP_PROPAGATE_DIAGONAL = 8,
+  SB2_OP_PROPAGATE_SYMMETRIC = 9
 } sb2_op;
 
 /* Largest basis size and history length accepted. */
@@ -243,6 +245,22 @@ typedef enum {
  * or flags), SB2_EWORKSPACE.                                                  */
 int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
                        void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream);
+
+/* sb2_gkba_propagate_vertex -- sb2_gkba_propagate for a special vertex of
+ * Sec. III (Sec. IV runs its chains this way), float64 throughout.  Per step
+ * n exactly the scheme of sb2_gkba_propagate, with
+ *   Sigma_HF (Eq. 12 for the vertex):  diagonal basis  diag(U_i rho_ii),
+ *                                      symmetric basis 2 diag(sum_k V_ik rho_kk) - V o rho
+ *   I_n: the collision integral of sb2_collision_vertex (self-energy of Eq. 14
+ *        or Eqs. 16-17) with the supplied propagators U(t_n, t_k).
+ * vertex, vparam as for sb2_collision_vertex; state arrays, flags and errors
+ * as for sb2_gkba_propagate (no prec argument).  Workspace:
+ * sb2_workspace_size(SB2_OP_PROPAGATE_DIAGONAL or SB2_OP_PROPAGATE_SYMMETRIC,
+ * N, n0 + nsteps, any prec).  Errors: as sb2_gkba_propagate; SB2_EINVAL for
+ * an unknown vertex.                                                          */
+int sb2_gkba_propagate_vertex(int N, int n0, int nsteps, int vertex, const double* vparam, const void* h,
+                              void* rho_hist, void* U_hist, void* I_hist, double dt, int flags, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* One system of a batched collision-integral evaluation. */
 typedef struct {

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2, "bf16x6": 3}   # bf16x6: recognised, not built
 OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4, "propagate": 5,
-       "collision_diagonal": 6, "collision_symmetric": 7}
+       "collision_diagonal": 6, "collision_symmetric": 7, "propagate_diagonal": 8, "propagate_symmetric": 9}
 VERTICES = {"diagonal": 1, "symmetric": 2}
 PROP_HF, PROP_COLLISION = 1, 2
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
@@ -85,6 +85,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_v8_expand.argtypes = [_i, _vp, _vp, _vp]
         L.sb2_collision_vertex.restype = _i
         L.sb2_collision_vertex.argtypes = [_i, _i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _sz, _vp]
+        L.sb2_gkba_propagate_vertex.restype = _i
+        L.sb2_gkba_propagate_vertex.argtypes = [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
         L.sb2_gkba_propagate.restype = _i
         L.sb2_gkba_propagate.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         _lib = L
@@ -312,6 +314,31 @@ def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, 
     _call("sb2_gkba_propagate", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
           u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt), flags, p,
           ws.data_ptr(), ws.numel(), _stream(v.device))
+
+
+def sb2_gkba_propagate_vertex(vertex: str, param, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float,
+                              hf: bool = True, collision: bool = True, i_hist=None):
+    """sb2_gkba_propagate for a special vertex ('diagonal': param U (N,),
+    'symmetric': param V (N, N)), float64; state arrays as for
+    sb2_gkba_propagate, advanced in place."""
+    n = h.shape[0]
+    if vertex not in VERTICES:
+        raise ValueError(f"vertex must be one of {sorted(VERTICES)}, got {vertex!r}")
+    _check(param, "param", torch.float64, (n,) if vertex == "diagonal" else (n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (rho_hist.shape[0], n, n))
+    _check(u_hist, "u_hist", torch.complex128, (u_hist.shape[0], n, n))
+    if rho_hist.shape[0] < n0 + nsteps + 1 or u_hist.shape[0] < max(n0 + nsteps, 1):
+        raise ValueError("rho_hist / u_hist capacity too small for n0 + nsteps")
+    if i_hist is not None:
+        _check(i_hist, "i_hist", torch.complex128, (i_hist.shape[0], n, n))
+        if i_hist.shape[0] < n0 + nsteps:
+            raise ValueError("i_hist capacity too small for n0 + nsteps")
+    ws = workspace(sb2_workspace_size("propagate_" + vertex, n, n0 + nsteps, 0), h.device)
+    flags = (PROP_HF if hf else 0) | (PROP_COLLISION if collision else 0)
+    _call("sb2_gkba_propagate_vertex", n, int(n0), int(nsteps), VERTICES[vertex], param.data_ptr(), h.data_ptr(),
+          rho_hist.data_ptr(), u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt),
+          flags, ws.data_ptr(), ws.numel(), _stream(h.device))
 
 
 def sb2_collision_backward(v, h, rho_hist, dt, grad_i, prec="fp64"):

@@ -512,6 +512,28 @@ k_sigma_hf(int N, const double* __restrict__ v, const cplx* __restrict__ rho, co
   if (j < N) out[(i64)i * N + j] = h[(i64)i * N + j] + acc;
 }
 
+// h + Sigma_HF (Eq. 12) for the special vertices of Sec. III, written out:
+//   diagonal basis  (v_ijkl = U_i d_ij d_ik d_il): Sigma_HF = diag(U_i rho_ii)
+//   symmetric basis (v_ijkl = V_ij d_il d_jk):     Sigma_HF_ij = 2 d_ij sum_k V_ik rho_kk - V_ij rho_ij
+// p: U (N) or V (N x N, row-major).  One thread per element (i, j).
+__global__ void k_sigma_hf_vertex(int N, int symmetric, const double* __restrict__ p, const cplx* __restrict__ rho,
+                                  const cplx* __restrict__ h, int with_hf, cplx* __restrict__ out) {
+  const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (i64)N * N) return;
+  const int i = (int)(idx / N), j = (int)(idx - (i64)i * N);
+  cplx acc = h[idx];
+  if (with_hf) {
+    if (!symmetric) {
+      if (i == j) acc += p[i] * rho[idx];
+    } else {
+      if (i == j)
+        for (int k = 0; k < N; ++k) acc += 2.0 * p[(i64)i * N + k] * rho[(i64)k * N + k];
+      acc -= p[idx] * rho[idx];
+    }
+  }
+  out[idx] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Self-energy of the special vertices (Sec. III A, III B), float64, for T
 // slices of one kind: G[k] = G(t, t_k) and Gb[k] = Gbar (the opposite-kind

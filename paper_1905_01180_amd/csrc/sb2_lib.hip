@@ -234,28 +234,6 @@ size_t tune_bytes(int N, int T, int prec) {
 
 size_t rho_plan(int N) { return 4 * al((size_t)N * N * C128); }
 
-// Workspace of a propagation that ends with n_end + 1 densities: the
-// collision evaluations (at most n_end - 1 past times; the collision plan
-// grows with T) followed by the step's own N x N matrices and the staging
-// area of the propagator-history update.
-struct PropPlan {
-  size_t heff, ustep, I, T1, ex1, ex2, tmp, end;
-};
-PropPlan prop_plan(int N, int n_end, int prec) {
-  PropPlan p;
-  const size_t m = al((size_t)N * N * C128);
-  size_t o = n_end >= 2 ? al(coll_plan(N, n_end - 1, prec).end) : 0;
-  p.heff = o; o += m;
-  p.ustep = o; o += m;
-  p.I = o; o += m;
-  p.T1 = o; o += m;
-  p.ex1 = o; o += m;
-  p.ex2 = o; o += m;
-  p.tmp = o; o += al((size_t)(n_end > 1 ? n_end - 1 : 1) * N * N * C128);
-  p.end = o;
-  return p;
-}
-
 // Workspace of the special-vertex collision integrals: the GKBA history and
 // self-energy areas of coll_plan (no contraction chain), and for the symmetric
 // basis the float64 operands of the bubble and exchange products for a chunk
@@ -298,6 +276,29 @@ VertPlan vert_plan(int N, int T, int vertex) {
 }
 
 
+
+// Workspace of a propagation that ends with n_end + 1 densities: the
+// collision evaluations (at most n_end - 1 past times; the collision plan
+// grows with T; vertex != 0: the special-vertex plan) followed by the step's
+// own N x N matrices and the staging area of the propagator-history update.
+struct PropPlan {
+  size_t heff, ustep, I, T1, ex1, ex2, tmp, end;
+};
+PropPlan prop_plan(int N, int n_end, int prec, int vertex = 0) {
+  PropPlan p;
+  const size_t m = al((size_t)N * N * C128);
+  size_t o = 0;
+  if (n_end >= 2) o = al(vertex ? vert_plan(N, n_end - 1, vertex).end : coll_plan(N, n_end - 1, prec).end);
+  p.heff = o; o += m;
+  p.ustep = o; o += m;
+  p.I = o; o += m;
+  p.T1 = o; o += m;
+  p.ex1 = o; o += m;
+  p.ex2 = o; o += m;
+  p.tmp = o; o += al((size_t)(n_end > 1 ? n_end - 1 : 1) * N * N * C128);
+  p.end = o;
+  return p;
+}
 
 inline char* at(void* ws, size_t off) { return reinterpret_cast<char*>(ws) + off; }
 
@@ -1305,6 +1306,12 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
     case SB2_OP_COLLISION_SYMMETRIC:
       if (T < 1 || T > SB2_MAX_T) return 0;
       return vert_plan(N, T, SB2_VERTEX_SYMMETRIC).end;
+    case SB2_OP_PROPAGATE_DIAGONAL:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return prop_plan(N, T, SB2_FP64, SB2_VERTEX_DIAGONAL).end;
+    case SB2_OP_PROPAGATE_SYMMETRIC:
+      if (T < 1 || T > SB2_MAX_T) return 0;
+      return prop_plan(N, T, SB2_FP64, SB2_VERTEX_SYMMETRIC).end;
     default:
       return 0;
   }
@@ -1542,6 +1549,130 @@ hipError_t sigma_symmetric(int N, int T, const double* V, const cplx* G, const c
   return hipSuccess;
 }
 
+}  // extern "C"
+
+namespace {
+// Collision integral of a special vertex from given propagators U[k] =
+// U(t, t_k) (Eq. 10 with Eq. 11's propagators supplied), float64: the GKBA
+// functions as in collision_core, the self-energies of Eq. 14 or Eqs. 16-17,
+// and the sum over past times.
+hipError_t collision_vertex_core(int N, int T, int vertex, const double* vparam, const cplx* U, const void* rho_hist,
+                                 double dt, cplx* I_out, cplx* Sigma_out, const VertPlan& p, void* ws,
+                                 hipStream_t s) {
+  const i64 nn = (i64)N * N;
+  auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
+  hipError_t e;
+  {
+    StageTimer tm(5, s);
+    GemmArgs g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = U; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+    g.B = rho_hist; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+    g.C = P(p.X); g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = rho_hist; g.sAm = N; g.sAk = 1; g.sAbh = nn;
+    g.B = U; g.sBk = 1; g.sBn = N; g.sBbh = nn; g.conjB = 1;
+    g.C = P(p.Y); g.sCm = N; g.sCn = 1; g.sCbh = nn;
+    if ((e = zgemm(g, T, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gkba, dim3(blocks((long long)T * nn, 256)), dim3(256), 0, s, N, T, U, P(p.X), P(p.Y),
+                       P(p.Gl), P(p.Gg), P(p.Glb), P(p.Ggb));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    StageTimer tm(6, s);
+    if (vertex == SB2_VERTEX_DIAGONAL) {
+      const dim3 grid(blocks((long long)T * nn, 256));
+      hipLaunchKernelGGL(k_sigma_diag, grid, dim3(256), 0, s, N, T, vparam, P(p.Gl), P(p.Ggb), P(p.Sl));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_sigma_diag, grid, dim3(256), 0, s, N, T, vparam, P(p.Gg), P(p.Glb), P(p.Sg));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(k_real_to_c, dim3(blocks(nn, 256)), dim3(256), 0, s, nn, vparam, P(p.Vc));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = sigma_symmetric(N, T, vparam, P(p.Gl), P(p.Ggb), P(p.Sl), p, ws, s)) != hipSuccess) return e;
+      if ((e = sigma_symmetric(N, T, vparam, P(p.Gg), P(p.Glb), P(p.Sg), p, ws, s)) != hipSuccess) return e;
+    }
+  }
+  if (Sigma_out) {
+    const size_t bytes = (size_t)T * nn * C128;
+    if ((e = hipMemcpyAsync(Sigma_out, P(p.Sl), bytes, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(Sigma_out + (i64)T * nn, P(p.Sg), bytes, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return e;
+  }
+  return collision_terms(N, T, P(p.Sl), P(p.Sg), P(p.Glb), P(p.Ggb), P(p.terms), dt, I_out, s);
+}
+
+// Time steps n0 .. n_end - 1 of the propagation of Sec. II (Eqs. 8, 11, 12):
+// h_HF from hf(rho_n, heff), U_step = exp(-i h_HF dt), I_n from coll(n, U, I)
+// over the past times t_0 .. t_{n-1} (I_0 = 0), the exponential-Euler density
+// step and the propagator-history update.  hf and coll enqueue their work.
+template <class HF, class COLL>
+hipError_t propagate_steps(int N, int n0, int n_end, void* rho_hist, void* U_hist, void* I_hist, double dt,
+                           int flags, const PropPlan& p, void* ws, hipStream_t s, HF&& hf, COLL&& coll) {
+  const i64 nn = (i64)N * N;
+  const size_t mb = (size_t)nn * C128;
+  cplx* rho = reinterpret_cast<cplx*>(rho_hist);
+  cplx* U = reinterpret_cast<cplx*>(U_hist);
+  cplx* heff = reinterpret_cast<cplx*>(at(ws, p.heff));
+  cplx* ustep = reinterpret_cast<cplx*>(at(ws, p.ustep));
+  cplx* I = reinterpret_cast<cplx*>(at(ws, p.I));
+  cplx* T1 = reinterpret_cast<cplx*>(at(ws, p.T1));
+  cplx* ex1 = reinterpret_cast<cplx*>(at(ws, p.ex1));
+  cplx* ex2 = reinterpret_cast<cplx*>(at(ws, p.ex2));
+  cplx* tmp = reinterpret_cast<cplx*>(at(ws, p.tmp));
+  hipError_t e;
+  for (int n = n0; n < n_end; ++n) {
+    cplx* rho_n = rho + (i64)n * nn;
+    // h_HF(t_n) = h + Sigma_HF(rho_n) (Eq. 12), U_step = exp(-i h_HF dt) (Eq. 11)
+    if ((e = hf(rho_n, heff)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, heff, 0.0, -dt, ustep, ex1, ex2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // I_ns(t_n) over the past times t_0 .. t_{n-1} (Eq. 9)
+    if ((flags & SB2_PROP_COLLISION) && n > 0) {
+      if ((e = coll(n, U, rho, I)) != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(k_fill_u32, dim3(blocks(4 * nn, 256)), dim3(256), 0, s, reinterpret_cast<unsigned*>(I),
+                         (int)(4 * nn), 0u);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (I_hist && (e = hipMemcpyAsync(reinterpret_cast<cplx*>(I_hist) + (i64)n * nn, I, mb,
+                                      hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return e;
+    // rho_{n+1} = U_step rho_n U_step^dag - dt (I + I^dag) (Eq. 8, exponential Euler)
+    GemmArgs g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = ustep; g.sAm = N; g.sAk = 1;
+    g.B = rho_n; g.sBk = N; g.sBn = 1;
+    g.C = T1; g.sCm = N; g.sCn = 1;
+    if ((e = zgemm(g, 1, s)) != hipSuccess) return e;
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = T1; g.sAm = N; g.sAk = 1;
+    g.B = ustep; g.sBk = 1; g.sBn = N; g.conjB = 1;
+    g.C = ex1; g.sCm = N; g.sCn = 1;
+    if ((e = zgemm(g, 1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rho_finish, dim3(blocks(nn, 256)), dim3(256), 0, s, N, ex1, I, dt, rho_n + nn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // U(t_{n+1}, t_k) = U_step U(t_n, t_k) for k < n, U(t_{n+1}, t_n) = U_step
+    if (n > 0) {
+      g = gdef();
+      g.M = N; g.N = N; g.K = N;
+      g.A = ustep; g.sAm = N; g.sAk = 1; g.sAbh = 0;
+      g.B = U; g.sBk = N; g.sBn = 1; g.sBbh = nn;
+      g.C = tmp; g.sCm = N; g.sCn = 1; g.sCbh = nn;
+      if ((e = zgemm(g, n, s)) != hipSuccess) return e;
+      if ((e = hipMemcpyAsync(U, tmp, (size_t)n * mb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    }
+    if ((e = hipMemcpyAsync(U + (i64)n * nn, ustep, mb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
 int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const void* h, const void* rho_hist,
                          double dt, void* I_out, void* Sigma_out, void* ws, size_t ws_bytes, void* stream) {
   if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
@@ -1552,33 +1683,14 @@ int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const v
   SB2_ENTRY();
   SB2_CHECKS(ws, N, {2, vparam, vertex == SB2_VERTEX_DIAGONAL ? (i64)N : (i64)N * N}, {0, h, 1}, {0, rho_hist, T});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const i64 nn = (i64)N * N;
-  auto P = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
-  SB2_TRY(gkba_history(N, T, h, rho_hist, dt, P(p.U), P(p.X), P(p.Y), P(p.Gl), P(p.Gg), P(p.Glb), P(p.Ggb),
-                       P(p.ex1), P(p.ex2), s));
+  cplx* U = reinterpret_cast<cplx*>(at(ws, p.U));
   {
-    StageTimer tm(6, s);
-    if (vertex == SB2_VERTEX_DIAGONAL) {
-      const dim3 grid(blocks((long long)T * nn, 256));
-      hipLaunchKernelGGL(k_sigma_diag, grid, dim3(256), 0, s, N, T, vparam, P(p.Gl), P(p.Ggb), P(p.Sl));
-      SB2_TRY(hipGetLastError());
-      hipLaunchKernelGGL(k_sigma_diag, grid, dim3(256), 0, s, N, T, vparam, P(p.Gg), P(p.Glb), P(p.Sg));
-      SB2_TRY(hipGetLastError());
-    } else {
-      hipLaunchKernelGGL(k_real_to_c, dim3(blocks(nn, 256)), dim3(256), 0, s, nn, vparam, P(p.Vc));
-      SB2_TRY(hipGetLastError());
-      SB2_TRY(sigma_symmetric(N, T, vparam, P(p.Gl), P(p.Ggb), P(p.Sl), p, ws, s));
-      SB2_TRY(sigma_symmetric(N, T, vparam, P(p.Gg), P(p.Glb), P(p.Sg), p, ws, s));
-    }
+    StageTimer tm(5, s);
+    SB2_TRY(propagators(N, T, h, dt, U, reinterpret_cast<cplx*>(at(ws, p.ex1)),
+                        reinterpret_cast<cplx*>(at(ws, p.ex2)), s));
   }
-  if (Sigma_out) {
-    const size_t bytes = (size_t)T * nn * C128;
-    SB2_TRY(hipMemcpyAsync(Sigma_out, P(p.Sl), bytes, hipMemcpyDeviceToDevice, s));
-    SB2_TRY(hipMemcpyAsync(reinterpret_cast<cplx*>(Sigma_out) + (i64)T * nn, P(p.Sg), bytes,
-                           hipMemcpyDeviceToDevice, s));
-  }
-  SB2_TRY(collision_terms(N, T, P(p.Sl), P(p.Sg), P(p.Glb), P(p.Ggb), P(p.terms), dt,
-                          reinterpret_cast<cplx*>(I_out), s));
+  SB2_TRY(collision_vertex_core(N, T, vertex, vparam, U, rho_hist, dt, reinterpret_cast<cplx*>(I_out),
+                                reinterpret_cast<cplx*>(Sigma_out), p, ws, s));
   return SB2_OK;
 }
 
@@ -1610,63 +1722,44 @@ int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h
   SB2_ENTRY();
   SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, U_hist, (i64)n0 * N * N});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const i64 nn = (i64)N * N;
-  const size_t mb = (size_t)nn * C128;
-  cplx* rho = reinterpret_cast<cplx*>(rho_hist);
-  cplx* U = reinterpret_cast<cplx*>(U_hist);
-  cplx* heff = reinterpret_cast<cplx*>(at(ws, p.heff));
-  cplx* ustep = reinterpret_cast<cplx*>(at(ws, p.ustep));
-  cplx* I = reinterpret_cast<cplx*>(at(ws, p.I));
-  cplx* T1 = reinterpret_cast<cplx*>(at(ws, p.T1));
-  cplx* ex1 = reinterpret_cast<cplx*>(at(ws, p.ex1));
-  cplx* ex2 = reinterpret_cast<cplx*>(at(ws, p.ex2));
-  cplx* tmp = reinterpret_cast<cplx*>(at(ws, p.tmp));
-  for (int n = n0; n < n_end; ++n) {
-    cplx* rho_n = rho + (i64)n * nn;
-    // h_HF(t_n) = h + Sigma_HF(rho_n) (Eq. 12), U_step = exp(-i h_HF dt) (Eq. 11)
+  auto hf = [&](const cplx* rho_n, cplx* heff) {
     hipLaunchKernelGGL(k_sigma_hf, dim3(N), dim3(SIGMA_HF_THREADS), 0, s, N, v, rho_n,
                        reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff);
-    SB2_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, heff, 0.0, -dt, ustep, ex1, ex2);
-    SB2_TRY(hipGetLastError());
-    // I_ns(t_n) over the past times t_0 .. t_{n-1} (Eq. 9)
-    if ((flags & SB2_PROP_COLLISION) && n > 0) {
-      const CollPlan c = coll_plan(N, n, prec);
-      SB2_TRY(collision_core(N, n, v, U, rho, dt, I, nullptr, prec, c, ws, s));
-    } else {
-      hipLaunchKernelGGL(k_fill_u32, dim3(blocks(4 * nn, 256)), dim3(256), 0, s, reinterpret_cast<unsigned*>(I),
-                         (int)(4 * nn), 0u);
-      SB2_TRY(hipGetLastError());
-    }
-    if (I_hist) SB2_TRY(hipMemcpyAsync(reinterpret_cast<cplx*>(I_hist) + (i64)n * nn, I, mb,
-                                       hipMemcpyDeviceToDevice, s));
-    // rho_{n+1} = U_step rho_n U_step^dag - dt (I + I^dag) (Eq. 8, exponential Euler)
-    GemmArgs g = gdef();
-    g.M = N; g.N = N; g.K = N;
-    g.A = ustep; g.sAm = N; g.sAk = 1;
-    g.B = rho_n; g.sBk = N; g.sBn = 1;
-    g.C = T1; g.sCm = N; g.sCn = 1;
-    SB2_TRY(zgemm(g, 1, s));
-    g = gdef();
-    g.M = N; g.N = N; g.K = N;
-    g.A = T1; g.sAm = N; g.sAk = 1;
-    g.B = ustep; g.sBk = 1; g.sBn = N; g.conjB = 1;
-    g.C = ex1; g.sCm = N; g.sCn = 1;
-    SB2_TRY(zgemm(g, 1, s));
-    hipLaunchKernelGGL(k_rho_finish, dim3(blocks(nn, 256)), dim3(256), 0, s, N, ex1, I, dt, rho_n + nn);
-    SB2_TRY(hipGetLastError());
-    // U(t_{n+1}, t_k) = U_step U(t_n, t_k) for k < n, U(t_{n+1}, t_n) = U_step
-    if (n > 0) {
-      g = gdef();
-      g.M = N; g.N = N; g.K = N;
-      g.A = ustep; g.sAm = N; g.sAk = 1; g.sAbh = 0;
-      g.B = U; g.sBk = N; g.sBn = 1; g.sBbh = nn;
-      g.C = tmp; g.sCm = N; g.sCn = 1; g.sCbh = nn;
-      SB2_TRY(zgemm(g, n, s));
-      SB2_TRY(hipMemcpyAsync(U, tmp, (size_t)n * mb, hipMemcpyDeviceToDevice, s));
-    }
-    SB2_TRY(hipMemcpyAsync(U + (i64)n * nn, ustep, mb, hipMemcpyDeviceToDevice, s));
-  }
+    return hipGetLastError();
+  };
+  auto coll = [&](int n, const cplx* U, const cplx* rho, cplx* I) {
+    const CollPlan c = coll_plan(N, n, prec);
+    return collision_core(N, n, v, U, rho, dt, I, nullptr, prec, c, ws, s);
+  };
+  SB2_TRY(propagate_steps(N, n0, n_end, rho_hist, U_hist, I_hist, dt, flags, p, ws, s, hf, coll));
+  return SB2_OK;
+}
+
+int sb2_gkba_propagate_vertex(int N, int n0, int nsteps, int vertex, const double* vparam, const void* h,
+                              void* rho_hist, void* U_hist, void* I_hist, double dt, int flags, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
+  if (!vparam || !h || !rho_hist || !U_hist || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  if (vertex != SB2_VERTEX_DIAGONAL && vertex != SB2_VERTEX_SYMMETRIC) return SB2_EINVAL;
+  if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
+  const int n_end = n0 + nsteps;
+  const PropPlan p = prop_plan(N, n_end, SB2_FP64, vertex);
+  if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, vparam, vertex == SB2_VERTEX_DIAGONAL ? (i64)N : (i64)N * N}, {0, h, 1},
+             {0, rho_hist, n0 + 1}, {1, U_hist, (i64)n0 * N * N});
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int sym = vertex == SB2_VERTEX_SYMMETRIC ? 1 : 0;
+  auto hf = [&](const cplx* rho_n, cplx* heff) {
+    hipLaunchKernelGGL(k_sigma_hf_vertex, dim3(blocks((long long)N * N, 256)), dim3(256), 0, s, N, sym, vparam,
+                       rho_n, reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff);
+    return hipGetLastError();
+  };
+  auto coll = [&](int n, const cplx* U, const cplx* rho, cplx* I) {
+    const VertPlan vp = vert_plan(N, n, vertex);
+    return collision_vertex_core(N, n, vertex, vparam, U, rho, dt, I, nullptr, vp, ws, s);
+  };
+  SB2_TRY(propagate_steps(N, n0, n_end, rho_hist, U_hist, I_hist, dt, flags, p, ws, s, hf, coll));
   return SB2_OK;
 }
 

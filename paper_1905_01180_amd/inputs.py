@@ -137,6 +137,33 @@ def rho_history(n: int, t: int, dt: float, g: np.random.Generator, kind: str = "
     return np.ascontiguousarray(0.5 * (hist + hist.conj().transpose(0, 2, 1)))
 
 
+def chain_hopping(n: int, hop: float = -1.0) -> np.ndarray:
+    """Open chain of n sites with nearest-neighbour hopping `hop` (h_ij = hop for |i - j| = 1)."""
+    h = np.zeros((n, n), np.complex128)
+    idx = np.arange(n - 1)
+    h[idx, idx + 1] = hop
+    h[idx + 1, idx] = hop
+    return h
+
+
+def hubbard_onsite(n: int, u: float = 1.0) -> np.ndarray:
+    """On-site interaction U_i = u of the diagonal (Hubbard) basis."""
+    return np.full(n, float(u))
+
+
+def ohno_matrix(n: int, u: float = 1.0) -> np.ndarray:
+    """Long-range interaction of the Ohno model, V_ij = u / sqrt(1 + |i - j|^2)."""
+    idx = np.arange(n)
+    return u / np.sqrt(1.0 + (idx[:, None] - idx[None, :]) ** 2.0)
+
+
+def left_half_density(n: int) -> np.ndarray:
+    """Density matrix with the n // 2 leftmost sites filled and the rest empty:
+    the state that a strong confinement potential on the left half gives with
+    n // 2 particles per spin."""
+    return np.diag(np.concatenate([np.ones(n // 2), np.zeros(n - n // 2)])).astype(np.complex128)
+
+
 @dataclasses.dataclass
 class System:
     """One synthetic GKBA system: frozen h, dense real v, rho history, dt."""

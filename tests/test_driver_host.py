@@ -109,3 +109,37 @@ def test_vertex_argument_errors_and_workspace(L):
     assert 0 < ws("collision_diagonal", 10, 5) < ws("collision_symmetric", 10, 5)
     # the symmetric-basis exchange operands are bounded by chunking (about 1 GiB)
     assert ws("collision_symmetric", 128, 2000) - ws("collision_diagonal", 128, 2000) < (1 << 31)
+
+
+def test_vertex_propagation_argument_errors_and_workspace(L):
+    p = L.sb2_gkba_propagate_vertex
+    assert p(0, 0, 1, 1, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, -1, 1, 1, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, 0, 0, 1, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, 0, 1, 5, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -1
+    assert p(8, 0, 1, 2, None, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -1
+    assert p(8, 0, 1, 2, FAKE, FAKE, FAKE, FAKE, None, 0.05, 8, FAKE, BIG, None) == -1
+    assert p(8, 0, 1, 2, FAKE, FAKE, FAKE, FAKE, None, float("inf"), 3, FAKE, BIG, None) == -1
+    assert p(8, 0, 4, 1, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, 64, None) == -3
+    ws = _lib.sb2_workspace_size
+    for vertex in ("diagonal", "symmetric"):
+        for n in (1, 10, 64):
+            for t in (1, 2, 50, 5000):
+                # a propagation ending at step t + 1 evaluates vertex collisions up to T = t
+                assert ws("propagate_" + vertex, n, t + 1) >= ws("collision_" + vertex, n, t)
+    assert ws("propagate_diagonal", 10, 5000) < ws("propagate", 10, 5000, "fp64")
+
+
+def test_vertex_mean_field_closed_forms():
+    # the HF self-energy the vertex propagation uses, written out for the two
+    # vertices, equals Eq. 12 evaluated with the materialised vertex tensor
+    from oracle import sb2_oracle as o
+    from paper_1905_01180_amd import inputs as gen
+    g = np.random.default_rng(17)
+    n = 6
+    rho = gen.density_matrix(n, g)
+    u = g.uniform(0.2, 1.0, n)
+    assert np.abs(o.sigma_hf(o.vertex_diagonal(u), rho) - np.diag(u * np.diag(rho))).max() < 1e-15
+    vm = gen.ohno_matrix(n, 0.9)
+    want = 2.0 * np.diag(vm @ np.diag(rho)) - vm * rho
+    assert np.abs(o.sigma_hf(o.vertex_symmetric(vm), rho) - want).max() < 1e-14
