@@ -194,6 +194,10 @@ def main():
                     help="time whole GKBA propagation steps (HF + second-Born collisions) from a history of --t steps")
     ap.add_argument("--vertex", choices=["diagonal", "symmetric"],
                     help="time the special-vertex collision integral (float64) at --n, --t")
+    ap.add_argument("--v", choices=["lowrank", "orbitals"], default="lowrank",
+                    help="interaction: the workloads' low-rank construction or real-orbital integrals (Eq. 4 symmetry)")
+    ap.add_argument("--packed", action="store_true",
+                    help="pass v as its 8-fold packed values (sb2_collision_v8; needs --v orbitals)")
     ap.add_argument("--chain", choices=["hubbard", "ohno"],
                     help="the paper's chain propagations of Sec. IV (N_b=10, J=-1, U=1; hubbard: diagonal "
                          "vertex, 5000 steps of 0.01; ohno: symmetric vertex, 2000 steps of 0.025), float64")
@@ -233,7 +237,15 @@ def main():
 
     cid = 2 if (args.n, args.t) == (100, 1000) else 99
     log(f"generating inputs N={args.n} T={args.t}")
-    s = gen.make_system(args.n, args.t, config_id=cid)
+    if args.packed and args.v != "orbitals":
+        print("--packed needs an interaction with the 8-fold symmetry: add --v orbitals", file=sys.stderr)
+        sys.exit(2)
+    s = gen.make_system(args.n, args.t, config_id=cid, v_kind=args.v)
+    if args.v != "lowrank":
+        args.no_error = True             # the stored oracle values belong to the low-rank interaction
+    if args.packed:
+        from paper_1905_01180_amd import v8
+        vp = torch.from_numpy(v8.pack(s.v)).to(dev)
     v = torch.from_numpy(s.v).to(dev)
     h = torch.from_numpy(s.h).to(dev)
     rho = torch.from_numpy(s.rho_hist).to(dev)
@@ -249,6 +261,8 @@ def main():
         del src, dst
 
     def run(prec):
+        if args.packed:
+            return _lib.sb2_collision_v8(vp, h, rho, s.dt, prec)
         return _lib.sb2_collision(v, h, rho, s.dt, prec)
 
     tuned = None
@@ -361,7 +375,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
         "config": {"workload": f"GKBA collision integral, N={args.n} basis, T={args.t} past times, dt={s.dt}",
-                   "N": args.n, "T": args.t, "prec": args.prec},
+                   "N": args.n, "T": args.t, "prec": args.prec,
+                   **({"interaction": args.v} if args.v != "lowrank" else {}),
+                   **({"v_format": "8-fold packed"} if args.packed else {})},
         "tflops_algorithmic": flops_step * value / 1e12,
         "roofline": roof, "cpu_baseline": cpu, "rel_err": err, "steps_per_s_by_prec": compare or None,
         "stages": stages, "kernel_hash": kernel_hash(), "tuning": tuned, "other_workloads": other,

@@ -211,6 +211,15 @@ int sb2_collision_vertex(int N, int T, int vertex, const double* vparam, const v
 size_t sb2_v8_count(int N);
 int sb2_v8_expand(int N, const double* packed, double* v, void* stream);
 
+/* sb2_collision_v8 -- sb2_collision with the interaction given as its 8-fold
+ * packed values (vpacked: sb2_v8_count(N) float64, layout as above; the full
+ * tensor is never formed: the layout kernels read the packed values
+ * directly).  Only for v with the symmetry of Eq. 4.  Results are bit for bit
+ * those of sb2_collision with v = sb2_v8_expand(vpacked).  Workspace:
+ * sb2_workspace_size(SB2_OP_COLLISION, N, T, prec).  Errors: as sb2_collision. */
+int sb2_collision_v8(int N, int T, const double* vpacked, const void* h, const void* rho_hist, double dt,
+                     void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream);
+
 /* Terms of the equation of motion included by sb2_gkba_propagate. */
 typedef enum {
   SB2_PROP_HF = 1,         /* Sigma_HF (Eq. 12) in the propagator and the commutator */

@@ -77,6 +77,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_rho_step.argtypes = [_i, _vp, _vp, _vp, _d, _vp, _vp, _sz, _vp]
         L.sb2_collision_noalloc.restype = _i
         L.sb2_collision_noalloc.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp]
+        L.sb2_collision_v8.restype = _i
+        L.sb2_collision_v8.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
         L.sb2_collision_prop.restype = _i
         L.sb2_collision_prop.argtypes = [_i, _i, _vp, _vp, _vp, _d, _vp, _vp, _i, _vp, _sz, _vp]
         L.sb2_v8_count.restype = _sz
@@ -260,6 +262,22 @@ def sb2_collision_prop(v: torch.Tensor, u_hist: torch.Tensor, rho_hist: torch.Te
     _call("sb2_collision_prop", n, t, v.data_ptr(), u_hist.data_ptr(), rho_hist.data_ptr(), float(dt),
           out.data_ptr(), sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(),
           _stream(v.device))
+    return (out, sig) if return_sigma else out
+
+
+def sb2_collision_v8(packed: torch.Tensor, h: torch.Tensor, rho_hist: torch.Tensor, dt: float, prec="fp64",
+                     return_sigma: bool = False):
+    """sb2_collision with v given as its 8-fold packed values (sb2_v8_count(N),)."""
+    t, n = rho_hist.shape[0], rho_hist.shape[1]
+    _check(packed, "packed", torch.float64, (int(lib().sb2_v8_count(n)),))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (t, n, n))
+    p = _prec(prec)
+    ws = workspace(sb2_workspace_size("collision", n, t, p), h.device)
+    out = torch.empty((n, n), dtype=torch.complex128, device=h.device)
+    sig = torch.empty((2, t, n, n), dtype=torch.complex128, device=h.device) if return_sigma else None
+    _call("sb2_collision_v8", n, t, packed.data_ptr(), h.data_ptr(), rho_hist.data_ptr(), float(dt), out.data_ptr(),
+          sig.data_ptr() if sig is not None else None, p, ws.data_ptr(), ws.numel(), _stream(h.device))
     return (out, sig) if return_sigma else out
 
 

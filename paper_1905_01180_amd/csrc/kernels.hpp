@@ -328,6 +328,21 @@ __global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cpl
   }
 }
 
+// Element v_abcd of the interaction tensor as the layout kernels read it:
+// dense row-major (v[((a N + b) N + c) N + d]) or 8-fold packed (Eq. 4: one
+// value per unordered pair of the unordered pairs {a, d} and {b, c},
+// packed[tri(tri(a, d), tri(b, c))] with tri(x, y) = max (max + 1) / 2 + min).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ i64 v8_tri(i64 a, i64 b) {
+  const i64 hi = a > b ? a : b, lo = a > b ? b : a;
+  return hi * (hi + 1) / 2 + lo;
+}
+template <bool PACKED>
+__device__ __forceinline__ double v_at(const double* __restrict__ v, int N, int a, int b, int c, int d) {
+  if constexpr (PACKED) return v[v8_tri(v8_tri(a, d), v8_tri(b, c))];
+  else return v[(((i64)a * N + b) * N + c) * N + d];
+}
+
 // ---------------------------------------------------------------------------
 // Interaction layouts for the contraction chain:
 //   W_T[x][m], x = (j N + s) N + q:  w_mqsj = 2 v_mqsj - v_qmsj   (row pitch KpW)
@@ -336,16 +351,17 @@ __global__ void k_pack(int N, int npairs, const cplx* __restrict__ Gl, const cpl
 // Stored in the bulk type, or (split float16) as hi / lo planes of
 // x 2^e with 2^e from the recorded max (two passes: k_max_vw, then the writers).
 // ---------------------------------------------------------------------------
+template <bool PACKED>
 __global__ void __launch_bounds__(256) k_max_vw(int N, const double* __restrict__ v, unsigned* vmax,
                                                  unsigned* wmax) {
   const int m = blockIdx.x / N, q = blockIdx.x % N;
-  const i64 nn = (i64)N * N;
-  const double* a = v + ((i64)m * N + q) * nn;
-  const double* b = v + ((i64)q * N + m) * nn;
+  const int nn = N * N;
   float mv = 0.f, mw = 0.f;
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-    mv = fmaxf(mv, fabsf((float)a[e]));
-    mw = fmaxf(mw, fabsf((float)(2.0 * a[e] - b[e])));
+    const int s = e / N, j = e - (e / N) * N;
+    const double a = v_at<PACKED>(v, N, m, q, s, j), b = v_at<PACKED>(v, N, q, m, s, j);
+    mv = fmaxf(mv, fabsf((float)a));
+    mw = fmaxf(mw, fabsf((float)(2.0 * a - b)));
   }
   block_atomic_max(mv, vmax);
   __syncthreads();
@@ -365,7 +381,7 @@ __device__ __forceinline__ void put_val<_Float16>(_Float16* base, i64 plane, i64
 }
 
 // one workgroup per (s, j-block of 16, m-block of 8); LDS tile [q][j][m]
-template <typename T>
+template <typename T, bool PACKED>
 __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* __restrict__ v, T* __restrict__ W,
                                                   i64 plane, const unsigned* wmax) {
   __shared__ float tile[128][16][9];
@@ -373,7 +389,6 @@ __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* _
   const int s = blockIdx.x / (nj * nm);
   const int rem = blockIdx.x - s * nj * nm;
   const int j0 = (rem / nm) * 16, m0 = (rem % nm) * 8;
-  const i64 nn = (i64)N * N;
   const float sc = split_scale(wmax);
   // read: for (mm, q): 16 consecutive j of v[m][q][s][j] and v[q][m][s][j]
   for (int L = threadIdx.x; L < 8 * N * 16; L += blockDim.x) {
@@ -382,8 +397,8 @@ __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* _
     const int m = m0 + mm, j = j0 + jj;
     float w = 0.f;
     if (m < N && j < N) {
-      const double a = v[((i64)m * N + q) * nn + (i64)s * N + j];
-      const double b = v[((i64)q * N + m) * nn + (i64)s * N + j];
+      const double a = v_at<PACKED>(v, N, m, q, s, j);
+      const double b = v_at<PACKED>(v, N, q, m, s, j);
       w = (float)(2.0 * a - b);
       if constexpr (sizeof(T) == 8) w = 0.f;    // float64 path re-reads below in full precision
     }
@@ -401,7 +416,7 @@ __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* _
       double val = 0.0;
       if (m < N) {
         if constexpr (sizeof(T) == 8) {
-          val = 2.0 * v[((i64)m * N + q) * nn + (i64)s * N + j] - v[((i64)q * N + m) * nn + (i64)s * N + j];
+          val = 2.0 * v_at<PACKED>(v, N, m, q, s, j) - v_at<PACKED>(v, N, q, m, s, j);
         } else {
           val = tile[q][jj][mm];
         }
@@ -412,12 +427,11 @@ __global__ void __launch_bounds__(256) k_prep_wt(int N, int KpW, const double* _
 }
 
 // one workgroup per (i, p): 32 x 32 LDS transposes of the (r, n) block
-template <typename T>
+template <typename T, bool PACKED>
 __global__ void __launch_bounds__(256) k_prep_vpt(int N, i64 KpV, i64 nstride, const double* __restrict__ v,
                                                    T* __restrict__ Vp, i64 plane, const unsigned* vmax) {
   __shared__ double tile[32][33];
   const int i = blockIdx.x / N, p = blockIdx.x % N;
-  const i64 nn = (i64)N * N;
   const float sc = split_scale(vmax);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r0 = 0; r0 < N; r0 += 32)
@@ -425,7 +439,7 @@ __global__ void __launch_bounds__(256) k_prep_vpt(int N, i64 KpV, i64 nstride, c
       __syncthreads();
       for (int yy = ty; yy < 32; yy += 8) {
         const int r = r0 + yy, n = n0 + tx;
-        tile[yy][tx] = (r < N && n < N) ? v[(((i64)i * N + r) * N + p) * N + n] : 0.0;
+        tile[yy][tx] = (r < N && n < N) ? v_at<PACKED>(v, N, i, r, p, n) : 0.0;
       }
       __syncthreads();
       for (int yy = ty; yy < 32; yy += 8) {
@@ -611,11 +625,6 @@ __global__ void k_real_to_c(i64 n, const double* __restrict__ x, cplx* __restric
 //   packed[ tri(P, Q) ],  P = pair(i, l), Q = pair(j, k),
 //   tri(P, Q) = max(P,Q) (max(P,Q) + 1) / 2 + min(P,Q).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ i64 v8_tri(i64 a, i64 b) {
-  const i64 hi = a > b ? a : b, lo = a > b ? b : a;
-  return hi * (hi + 1) / 2 + lo;
-}
-
 // v[i][j][k][l] = packed[tri(pair(i, l), pair(j, k))] for all N^4 entries.
 __global__ void k_v8_expand(int N, const double* __restrict__ packed, double* __restrict__ v) {
   const i64 nn = (i64)N * N, total = nn * nn;

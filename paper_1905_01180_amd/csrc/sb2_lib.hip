@@ -421,22 +421,23 @@ int run_checks(hipStream_t s, void* scr, int N, std::initializer_list<CheckItem>
 // ---------------------------------------------------------------------------
 // The chain for one chunk of ns slices
 // ---------------------------------------------------------------------------
-template <typename T>
+// v: the dense tensor, or (PACKED) its 8-fold packed values (Eq. 4)
+template <typename T, bool PACKED>
 hipError_t prep_interaction(int N, const double* v, const ChainPlan& p, void* ws, int prec, hipStream_t s) {
   unsigned* scal = reinterpret_cast<unsigned*>(at(ws, p.scal));
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, scal, (int)S_NWORDS, 0u);
   const bool h = prec == SB2_SPLIT_FP16;
-  if (h) hipLaunchKernelGGL(k_max_vw, dim3(N * N), dim3(256), 0, s, N, v, scal + S_VMAX, scal + S_WMAX);
+  if (h) hipLaunchKernelGGL(k_max_vw<PACKED>, dim3(N * N), dim3(256), 0, s, N, v, scal + S_VMAX, scal + S_WMAX);
   const int nj = (N + 15) / 16, nm = (N + 7) / 8;
   const i64 planeW = (i64)N * N * N * p.KpW, planeV = (i64)N * p.KpV;
-  hipLaunchKernelGGL(k_prep_wt<T>, dim3(N * nj * nm), dim3(256), 0, s, N, (int)p.KpW, v,
+  hipLaunchKernelGGL((k_prep_wt<T, PACKED>), dim3(N * nj * nm), dim3(256), 0, s, N, (int)p.KpW, v,
                      reinterpret_cast<T*>(at(ws, p.w)), planeW, h ? scal + S_WMAX : nullptr);
   if (p.chunked) {                               // zero n-block padding
     const long long words = (long long)N * p.KpV;  // two float16 planes: N KpV 32-bit words
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks(words, 256)), dim3(256), 0, s,
                        reinterpret_cast<unsigned*>(at(ws, p.vp)), (int)words, 0u);
   }
-  hipLaunchKernelGGL(k_prep_vpt<T>, dim3(N * N), dim3(256), 0, s, N, p.KpV, p.chunked ? p.KB : (i64)N * N, v,
+  hipLaunchKernelGGL((k_prep_vpt<T, PACKED>), dim3(N * N), dim3(256), 0, s, N, p.KpV, p.chunked ? p.KB : (i64)N * N, v,
                      reinterpret_cast<T*>(at(ws, p.vp)), planeV, h ? scal + S_VMAX : nullptr);
   return hipGetLastError();
 }
@@ -573,11 +574,17 @@ hipError_t pack(int N, int npairs, const void* Gl, const void* Gg, const void* G
   return hipGetLastError();
 }
 
-hipError_t prep_dispatch(int prec, int N, const double* v, const ChainPlan& p, void* ws, hipStream_t s) {
+hipError_t prep_dispatch(int prec, int N, const double* v, const ChainPlan& p, void* ws, hipStream_t s,
+                         bool packed = false) {
   StageTimer tm(4, s);
-  if (prec == SB2_FP64) return prep_interaction<double>(N, v, p, ws, prec, s);
-  if (prec == SB2_FP32) return prep_interaction<float>(N, v, p, ws, prec, s);
-  return prep_interaction<_Float16>(N, v, p, ws, prec, s);
+  if (packed) {
+    if (prec == SB2_FP64) return prep_interaction<double, true>(N, v, p, ws, prec, s);
+    if (prec == SB2_FP32) return prep_interaction<float, true>(N, v, p, ws, prec, s);
+    return prep_interaction<_Float16, true>(N, v, p, ws, prec, s);
+  }
+  if (prec == SB2_FP64) return prep_interaction<double, false>(N, v, p, ws, prec, s);
+  if (prec == SB2_FP32) return prep_interaction<float, false>(N, v, p, ws, prec, s);
+  return prep_interaction<_Float16, false>(N, v, p, ws, prec, s);
 }
 
 hipError_t pack_dispatch(int prec, int N, int np, const void* Gl, const void* Gg, const void* Glb,
@@ -590,9 +597,10 @@ hipError_t pack_dispatch(int prec, int N, int np, const void* Gl, const void* Gg
 // Self-energies of `pairs` pairs (Gl[k], Gg[k]) -> S_less[k], S_great[k].
 hipError_t sigma_pairs(int prec, int N, int pairs, const double* v, const void* Gl, const void* Gg,
                        const void* Glb, const void* Ggb, int from_g, cplx* S_less, cplx* S_great,
-                       cplx* O_less, cplx* O_great, const ChainPlan& p, void* ws, hipStream_t s) {
+                       cplx* O_less, cplx* O_great, const ChainPlan& p, void* ws, hipStream_t s,
+                       bool packed = false) {
   const size_t nn = (size_t)N * N;
-  hipError_t e = prep_dispatch(prec, N, v, p, ws, s);
+  hipError_t e = prep_dispatch(prec, N, v, p, ws, s, packed);
   if (e != hipSuccess) return e;
   for (int k0 = 0; k0 < pairs; k0 += p.S) {
     const int np = pairs - k0 < p.S ? pairs - k0 : p.S;
@@ -1354,7 +1362,8 @@ hipError_t collision_terms(int N, int T, const cplx* Sl, const cplx* Sg, const c
 // with Eq. 11's propagators supplied): X_k = U_k rho_k, Y_k = rho_k U_k^dag,
 // the four GKBA functions, the self-energy chain and the k-sum.
 hipError_t collision_core(int N, int T, const double* v, const cplx* U, const void* rho_hist, double dt,
-                          cplx* I_out, cplx* Sigma_out, int prec, const CollPlan& c, void* ws, hipStream_t s) {
+                          cplx* I_out, cplx* Sigma_out, int prec, const CollPlan& c, void* ws, hipStream_t s,
+                          bool packed = false) {
   const i64 nn = (i64)N * N;
   cplx* X = reinterpret_cast<cplx*>(at(ws, c.X));
   cplx* Y = reinterpret_cast<cplx*>(at(ws, c.Y));
@@ -1388,7 +1397,8 @@ hipError_t collision_core(int N, int T, const double* v, const cplx* U, const vo
 
   cplx* Ol = Sigma_out;
   cplx* Og = Sigma_out ? Ol + (i64)T * nn : nullptr;
-  if ((e = sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s)) != hipSuccess) return e;
+  if ((e = sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s, packed)) != hipSuccess)
+    return e;
   return collision_terms(N, T, Sl, Sg, Glb, Ggb, terms, dt, I_out, s);
 }
 
@@ -1486,6 +1496,27 @@ int sb2_collision_noalloc(int N, int T, const double* v, const void* h, const vo
   }
   SB2_TRY(collision_core(N, T, v, U, rho_hist, dt, reinterpret_cast<cplx*>(I_out),
                          reinterpret_cast<cplx*>(Sigma_out), prec, c, ws, s));
+  return SB2_OK;
+}
+
+int sb2_collision_v8(int N, int T, const double* vpacked, const void* h, const void* rho_hist, double dt,
+                     void* I_out, void* Sigma_out, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || T < 1 || T > SB2_MAX_T) return SB2_ESHAPE;
+  if (!vpacked || !h || !rho_hist || !I_out || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  SB2_PREC(prec);
+  const CollPlan c = coll_plan(N, T, prec);
+  if (ws_bytes < c.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  SB2_CHECKS(ws, N, {2, vpacked, (i64)sb2_v8_count(N)}, {0, h, 1}, {0, rho_hist, T});
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  cplx* U = reinterpret_cast<cplx*>(at(ws, c.U));
+  {
+    StageTimer tm(5, s);
+    SB2_TRY(propagators(N, T, h, dt, U, reinterpret_cast<cplx*>(at(ws, c.ex1)),
+                        reinterpret_cast<cplx*>(at(ws, c.ex2)), s));
+  }
+  SB2_TRY(collision_core(N, T, vpacked, U, rho_hist, dt, reinterpret_cast<cplx*>(I_out),
+                         reinterpret_cast<cplx*>(Sigma_out), prec, c, ws, s, true));
   return SB2_OK;
 }
 

@@ -79,3 +79,31 @@ def test_gpu_expand_is_exact(n):
     # the expansion is exactly symmetric; v itself only to its rounding (an orbit
     # representative is at most three generator steps from any member)
     assert np.abs(got - v).max() <= 3.0 * v8.symmetry_error(v) + 1e-300
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+@pytest.mark.parametrize("n,t", [(1, 2), (5, 3), (17, 4), (33, 3), (100, 2), (120, 2)])
+def test_gpu_packed_collision_is_bitwise_dense(n, t, prec):
+    # the layout kernels read the packed values directly; the result must be
+    # bit for bit the dense path's on the expanded tensor
+    import torch
+    from paper_1905_01180_amd import _lib
+    s = gen.make_system(n, t, config_id=240, system_id=n, v_kind="orbitals")
+    packed = torch.from_numpy(v8.pack(s.v)).to("cuda")
+    h, r = torch.from_numpy(s.h).to("cuda"), torch.from_numpy(s.rho_hist).to("cuda")
+    print(f"case: packed collision N={n} T={t} {prec}", flush=True)
+    got, gsig = _lib.sb2_collision_v8(packed, h, r, s.dt, prec, return_sigma=True)
+    dense = _lib.sb2_v8_expand(packed, n)
+    want, wsig = _lib.sb2_collision(dense, h, r, s.dt, prec, return_sigma=True)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want) and torch.equal(gsig, wsig)
+    if n <= 33:
+        # and the oracle's self-energies (I itself cancels to rounding noise at N = 1)
+        from oracle import sb2_oracle as o
+        _, ref = o.collision(s.v, s.h, s.rho_hist, s.dt, return_sigma=True)
+        tol = 1e-11 if prec == "fp64" else 2e-6
+        gsig = gsig.cpu().numpy()
+        for k in range(t):
+            for kind in (0, 1):
+                assert np.abs(gsig[kind, k] - ref[k][kind]).max() < tol * np.abs(ref[k][kind]).max()
