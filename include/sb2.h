@@ -255,6 +255,21 @@ typedef enum {
 int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
                        void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream);
 
+/* sb2_gkba_propagate_switched -- sb2_gkba_propagate with a time-dependent
+ * interaction strength: the Hamiltonian is h + lambda(t) V, as in the
+ * adiabatic switching by which Sec. II prepares a correlated state from an
+ * uncorrelated one.  lambda: device array of n0 + nsteps float64 values,
+ * lambda[m] = lambda(t_m).  The HF self-energy at t_n carries lambda(t_n) and
+ * the second-Born self-energy Sigma(t_n, t_k), whose two interaction lines sit
+ * at t_n and t_k, carries lambda(t_n) lambda(t_k):
+ *   h_HF(t_n) = h + lambda_n Sigma_HF(rho_n),
+ *   I_n = dt lambda_n sum_k lambda_k [Sigma^>_k G^<(t_k,t_n) - Sigma^<_k G^>(t_k,t_n)],
+ * everything else as in sb2_gkba_propagate (same workspace size).
+ * Errors: as sb2_gkba_propagate; SB2_EINVAL for lambda == NULL.            */
+int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist,
+                                void* U_hist, void* I_hist, const double* lambda, double dt, int flags, int prec,
+                                void* ws, size_t ws_bytes, void* stream);
+
 /* sb2_gkba_propagate_vertex -- sb2_gkba_propagate for a special vertex of
  * Sec. III (Sec. IV runs its chains this way), float64 throughout.  Per step
  * n exactly the scheme of sb2_gkba_propagate, with

@@ -89,6 +89,9 @@ def lib() -> ctypes.CDLL:
         L.sb2_collision_vertex.argtypes = [_i, _i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _sz, _vp]
         L.sb2_gkba_propagate_vertex.restype = _i
         L.sb2_gkba_propagate_vertex.argtypes = [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
+        L.sb2_gkba_propagate_switched.restype = _i
+        L.sb2_gkba_propagate_switched.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz,
+                                                  _vp]
         L.sb2_gkba_propagate.restype = _i
         L.sb2_gkba_propagate.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         _lib = L
@@ -309,11 +312,13 @@ def sb2_collision_vertex(vertex: str, param: torch.Tensor, h: torch.Tensor, rho_
 
 
 def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, prec="fp64", hf: bool = True,
-                       collision: bool = True, i_hist=None):
+                       collision: bool = True, i_hist=None, switch=None):
     """Advance the propagation state in place from step n0 to n0 + nsteps.
 
     rho_hist (C, N, N) with C >= n0 + nsteps + 1, u_hist and i_hist (C', N, N)
     with C' >= n0 + nsteps (i_hist optional); all complex128 on the device.
+    switch: optional device float64 coupling history lambda(t_m) (the
+    interaction is lambda(t) v; sb2_gkba_propagate_switched).
     """
     n = h.shape[0]
     _check(v, "v", torch.float64, (n, n, n, n))
@@ -329,6 +334,15 @@ def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, 
     p = _prec(prec)
     ws = workspace(sb2_workspace_size("propagate", n, n0 + nsteps, p), v.device)
     flags = (PROP_HF if hf else 0) | (PROP_COLLISION if collision else 0)
+    if switch is not None:
+        # time-dependent coupling: switch[m] = lambda(t_m), m < n0 + nsteps (device float64)
+        _check(switch, "switch", torch.float64, (switch.shape[0],))
+        if switch.shape[0] < n0 + nsteps:
+            raise ValueError("switch must hold lambda(t_m) for every m < n0 + nsteps")
+        _call("sb2_gkba_propagate_switched", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(),
+              rho_hist.data_ptr(), u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None,
+              switch.data_ptr(), float(dt), flags, p, ws.data_ptr(), ws.numel(), _stream(v.device))
+        return
     _call("sb2_gkba_propagate", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
           u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt), flags, p,
           ws.data_ptr(), ws.numel(), _stream(v.device))

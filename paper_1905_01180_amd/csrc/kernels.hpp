@@ -479,13 +479,22 @@ __global__ void k_reduce_sigma(int N, int nslices, int nz, const cplx* __restric
 }
 
 // I = dt sum_k terms[k], the k-sum in k order in float64.
-__global__ void k_sum_terms(int N, int T, const cplx* __restrict__ terms, double dt, cplx* __restrict__ I) {
+// I = dt sum_k terms_k, k in order; with a time-dependent coupling lam (lam[k]
+// = lambda(t_k), the self-energy Sigma(t, t_k) carrying lambda(t) lambda(t_k))
+// I = dt lam[now] sum_k lam[k] terms_k.
+__global__ void k_sum_terms(int N, int T, const cplx* __restrict__ terms, double dt, cplx* __restrict__ I,
+                            const double* __restrict__ lam, int now) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const i64 nn = (i64)N * N;
   if (e >= nn) return;
   cplx acc = mk(0, 0);
-  for (int k = 0; k < T; ++k) acc += terms[k * nn + e];
-  I[e] = acc * dt;
+  if (lam) {
+    for (int k = 0; k < T; ++k) acc += lam[k] * terms[k * nn + e];
+    I[e] = acc * (dt * lam[now]);
+  } else {
+    for (int k = 0; k < T; ++k) acc += terms[k * nn + e];
+    I[e] = acc * dt;
+  }
 }
 
 // rho_out = Y - dt (I + I^dag)
@@ -506,7 +515,7 @@ __global__ void k_rho_finish(int N, const cplx* __restrict__ Y, const cplx* __re
 constexpr int SIGMA_HF_THREADS = 128;
 __global__ void __launch_bounds__(SIGMA_HF_THREADS)
 k_sigma_hf(int N, const double* __restrict__ v, const cplx* __restrict__ rho, const cplx* __restrict__ h,
-           int with_hf, cplx* __restrict__ out) {
+           int with_hf, cplx* __restrict__ out, const double* __restrict__ lam, int now) {
   __shared__ cplx col[SIGMA_HF_THREADS];
   const int i = blockIdx.x, j = threadIdx.x;
   const i64 nn = (i64)N * N;
@@ -523,6 +532,7 @@ k_sigma_hf(int N, const double* __restrict__ v, const cplx* __restrict__ rho, co
       }
     }
   }
+  if (lam) acc *= lam[now];                               // coupling lambda(t_now)
   if (j < N) out[(i64)i * N + j] = h[(i64)i * N + j] + acc;
 }
 

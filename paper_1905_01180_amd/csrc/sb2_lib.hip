@@ -1233,7 +1233,7 @@ hipError_t collision_batched(int nsys, const sb2_system* sys, int prec, const Ba
     g.A = P(c.Sl); g.B = P(c.Ggb); g.alpha_re = -1.0; g.beta1 = 1;
     if ((e = zgemm(g, T, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, P(c.terms), sys[b].dt,
-                       reinterpret_cast<cplx*>(sys[b].I_out));
+                       reinterpret_cast<cplx*>(sys[b].I_out), (const double*)nullptr, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1342,7 +1342,8 @@ int sb2_sigma(int N, int B, const double* v, const void* Gl, const void* Gg, voi
 
 // I = dt sum_k [Sigma^>_k G^<(t_k,t) - Sigma^<_k G^>(t_k,t)] (Eq. 9), float64.
 hipError_t collision_terms(int N, int T, const cplx* Sl, const cplx* Sg, const cplx* Glb, const cplx* Ggb,
-                           cplx* terms, double dt, cplx* I_out, hipStream_t s) {
+                           cplx* terms, double dt, cplx* I_out, hipStream_t s, const double* lam = nullptr,
+                           int now = 0) {
   const i64 nn = (i64)N * N;
   StageTimer tm(7, s);
   GemmArgs g = gdef();
@@ -1354,7 +1355,7 @@ hipError_t collision_terms(int N, int T, const cplx* Sl, const cplx* Sg, const c
   if ((e = zgemm(g, T, s)) != hipSuccess) return e;
   g.A = Sl; g.B = Ggb; g.alpha_re = -1.0; g.beta1 = 1;
   if ((e = zgemm(g, T, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt, I_out);
+  hipLaunchKernelGGL(k_sum_terms, dim3(blocks(nn, 256)), dim3(256), 0, s, N, T, terms, dt, I_out, lam, now);
   return hipGetLastError();
 }
 
@@ -1363,7 +1364,7 @@ hipError_t collision_terms(int N, int T, const cplx* Sl, const cplx* Sg, const c
 // the four GKBA functions, the self-energy chain and the k-sum.
 hipError_t collision_core(int N, int T, const double* v, const cplx* U, const void* rho_hist, double dt,
                           cplx* I_out, cplx* Sigma_out, int prec, const CollPlan& c, void* ws, hipStream_t s,
-                          bool packed = false) {
+                          bool packed = false, const double* lam = nullptr, int now = 0) {
   const i64 nn = (i64)N * N;
   cplx* X = reinterpret_cast<cplx*>(at(ws, c.X));
   cplx* Y = reinterpret_cast<cplx*>(at(ws, c.Y));
@@ -1399,7 +1400,7 @@ hipError_t collision_core(int N, int T, const double* v, const cplx* U, const vo
   cplx* Og = Sigma_out ? Ol + (i64)T * nn : nullptr;
   if ((e = sigma_pairs(prec, N, T, v, Gl, Gg, Glb, Ggb, 0, Sl, Sg, Ol, Og, c.ch, ws, s, packed)) != hipSuccess)
     return e;
-  return collision_terms(N, T, Sl, Sg, Glb, Ggb, terms, dt, I_out, s);
+  return collision_terms(N, T, Sl, Sg, Glb, Ggb, terms, dt, I_out, s, lam, now);
 }
 
 int sb2_collision(int N, int T, const double* v, const void* h, const void* rho_hist, double dt, void* I_out,
@@ -1741,8 +1742,15 @@ int sb2_v8_expand(int N, const double* packed, double* v, void* stream) {
   return SB2_OK;
 }
 
-int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
-                       void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+// sb2_gkba_propagate, with an optional coupling history lam[m] = lambda(t_m)
+// (the interaction is lambda(t) v: Sigma_HF(t_n) carries lambda(t_n), the
+// self-energy Sigma(t_n, t_k) lambda(t_n) lambda(t_k)).
+int propagate_general(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
+                      void* I_hist, const double* lam, double dt, int flags, int prec, void* ws, size_t ws_bytes,
+                      void* stream) {
   if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
   if (!v || !h || !rho_hist || !U_hist || !ws || !finite_pos(dt)) return SB2_EINVAL;
   if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
@@ -1751,19 +1759,39 @@ int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h
   const PropPlan p = prop_plan(N, n_end, prec);
   if (ws_bytes < p.end) return SB2_EWORKSPACE;
   SB2_ENTRY();
-  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, U_hist, (i64)n0 * N * N});
+  SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, U_hist, (i64)n0 * N * N},
+             {2, lam, lam ? (i64)n_end : 0});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int now = 0;
   auto hf = [&](const cplx* rho_n, cplx* heff) {
+    now = (int)((rho_n - reinterpret_cast<const cplx*>(rho_hist)) / ((i64)N * N));
     hipLaunchKernelGGL(k_sigma_hf, dim3(N), dim3(SIGMA_HF_THREADS), 0, s, N, v, rho_n,
-                       reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff);
+                       reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff, lam, now);
     return hipGetLastError();
   };
   auto coll = [&](int n, const cplx* U, const cplx* rho, cplx* I) {
     const CollPlan c = coll_plan(N, n, prec);
-    return collision_core(N, n, v, U, rho, dt, I, nullptr, prec, c, ws, s);
+    return collision_core(N, n, v, U, rho, dt, I, nullptr, prec, c, ws, s, false, lam, n);
   };
   SB2_TRY(propagate_steps(N, n0, n_end, rho_hist, U_hist, I_hist, dt, flags, p, ws, s, hf, coll));
   return SB2_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
+                       void* I_hist, double dt, int flags, int prec, void* ws, size_t ws_bytes, void* stream) {
+  return propagate_general(N, n0, nsteps, v, h, rho_hist, U_hist, I_hist, nullptr, dt, flags, prec, ws, ws_bytes,
+                           stream);
+}
+
+int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist,
+                                void* U_hist, void* I_hist, const double* lambda, double dt, int flags, int prec,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!lambda) return SB2_EINVAL;
+  return propagate_general(N, n0, nsteps, v, h, rho_hist, U_hist, I_hist, lambda, dt, flags, prec, ws, ws_bytes,
+                           stream);
 }
 
 int sb2_gkba_propagate_vertex(int N, int n0, int nsteps, int vertex, const double* vparam, const void* h,

@@ -143,3 +143,11 @@ def test_vertex_mean_field_closed_forms():
     vm = gen.ohno_matrix(n, 0.9)
     want = 2.0 * np.diag(vm @ np.diag(rho)) - vm * rho
     assert np.abs(o.sigma_hf(o.vertex_symmetric(vm), rho) - want).max() < 1e-14
+
+
+def test_switched_propagation_arguments(L):
+    p = L.sb2_gkba_propagate_switched
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 3, 0, FAKE, BIG, None) == -1   # no lambda
+    assert p(0, 0, 2, FAKE, FAKE, FAKE, FAKE, None, FAKE, 0.05, 3, 0, FAKE, BIG, None) == -2
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, None, FAKE, 0.05, 3, 3, FAKE, BIG, None) == -5   # split BF16
+    assert p(8, 0, 4, FAKE, FAKE, FAKE, FAKE, None, FAKE, 0.05, 3, 0, FAKE, 64, None) == -3

@@ -204,3 +204,95 @@ def test_collision_and_rho_step_give_the_exact_correlation_part(case):
     assert _err(got, want) < 0.2 * scale
     bad = richardson(lambda dt: order2(lambda lam: frozen_h_rho(lam * v, h, rho0, dt, sign=-1.0)))[1]
     assert _err(bad, want) > 1.5 * scale
+
+
+# --- time-dependent coupling (adiabatic switching) ----------------------------
+#
+# With H(t) = h + lambda(t) V the second-Born self-energy Sigma(t, t') carries
+# lambda(t) lambda(t') (one interaction line at each time) and the HF
+# self-energy lambda(t): the switched propagation must again agree with exact
+# dynamics through O(v^2).  Placing lambda(t)^2 or lambda(t')^2 on Sigma
+# instead (planted below) must not.
+
+def ramp(t):
+    """A coupling that varies on the time scale of the collision integral's
+    memory (a slow switch-on would hide where lambda sits): on from zero,
+    then oscillating."""
+    return np.sin(0.5 * np.pi * min(t, 0.3) / 0.3) ** 2 * (1.0 + 0.6 * np.sin(2.0 * np.pi * t / 0.6))
+
+
+def exact_density_switched(h, v, orbitals, times, dt_exact=0.0025):
+    """As exact_density for H(t) = h + ramp(t) V, stepped with the midpoint
+    exponential of H (second order in dt_exact)."""
+    n = h.shape[0]
+    c = _annihilators(2 * n)
+    cd = [x.T for x in c]
+    dim = 1 << (2 * n)
+    h1 = np.zeros((dim, dim), complex)
+    for i in range(n):
+        for j in range(n):
+            for s in range(2):
+                h1 += h[i, j] * cd[2 * i + s] @ c[2 * j + s]
+    h2 = np.zeros((dim, dim))
+    for i, j, k, l in np.ndindex(n, n, n, n):
+        if v[i, j, k, l] != 0.0:
+            for s in range(2):
+                for t in range(2):
+                    h2 += 0.5 * v[i, j, k, l] * cd[2 * i + s] @ cd[2 * j + t] @ c[2 * k + t] @ c[2 * l + s]
+    psi = np.zeros(dim, complex)
+    psi[0] = 1.0
+    for a in range(orbitals.shape[1]):
+        for s in range(2):
+            psi = sum(orbitals[i, a] * cd[2 * i + s] for i in range(n)) @ psi
+    psi /= np.linalg.norm(psi)
+    out, t = [], 0.0
+    for target in times:
+        steps = int(round((target - t) / dt_exact))
+        for _ in range(steps):
+            e, p = np.linalg.eigh(h1 + ramp(t + 0.5 * dt_exact) * h2)
+            psi = p @ (np.exp(-1j * e * dt_exact) * (p.conj().T @ psi))
+            t += dt_exact
+        out.append([[psi.conj() @ (cd[2 * j] @ c[2 * i] @ psi) for j in range(n)] for i in range(n)])
+    return np.array(out)
+
+
+def switched_rho(v, h, rho0, dt, weight="product"):
+    """Switched propagation; weight='product' is the oracle, the others are
+    planted mistakes (lambda(t_n)^2 or lambda(t_k)^2 on Sigma(t_n, t_k))."""
+    idx = _idx(dt)
+    lam = np.array([ramp(m * dt) for m in range(idx[-1] + 1)])
+    if weight == "product":
+        return d.propagate(v, h, dt, idx[-1], d.new_state(rho0), switch=lam)["rho"][idx]
+    rho, u = [rho0], []
+    for n in range(idx[-1]):
+        us = o.propagator(h + lam[n] * o.sigma_hf(v, rho[n]), dt)
+        if n:
+            w = np.full(n, lam[n]) if weight == "now" else lam[:n]
+            i_n = d.collision_from_propagators(v, np.stack(u), np.stack(rho[:n]), dt, w,
+                                               lam[n] if weight == "now" else 1.0)
+            if weight == "past":
+                i_n = d.collision_from_propagators(v, np.stack(u), np.stack(rho[:n]), dt, lam[:n] ** 2, 1.0)
+        else:
+            i_n = 0 * h
+        rho.append(us @ rho[n] @ us.conj().T - dt * (i_n + i_n.conj().T))
+        u = [us @ x for x in u] + [us]
+    return np.stack(rho)[idx]
+
+
+def richardson2(fn):
+    """Two Richardson steps over DTS (removing the dt and dt^2 terms)."""
+    vals = [fn(dt) for dt in DTS]
+    r1, r2 = 2 * vals[1] - vals[0], 2 * vals[2] - vals[1]
+    return (4 * r2 - r1) / 3
+
+
+def test_switched_coupling_is_exact_through_second_order():
+    h, v, orb, rho0 = _case(3, 1, 5)
+    ex2 = order2(lambda lam: exact_density_switched(h, lam * v, orb, TIMES))
+    err = {w: _err(richardson2(lambda dt: order2(lambda lam: switched_rho(lam * v, h, rho0, dt, w))), ex2)
+           for w in ("product", "now", "past")}
+    scale = np.abs(ex2).max()
+    print(f"switched O(v^2): |rho2| {scale:.3e}, extrapolated error {err['product']:.3e}; "
+          f"lambda(t)^2: {err['now']:.3e}, lambda(t')^2: {err['past']:.3e}")
+    assert err["product"] < 0.01 * scale
+    assert err["now"] > 5 * err["product"] and err["past"] > 5 * err["product"]
