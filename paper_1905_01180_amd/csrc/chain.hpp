@@ -104,15 +104,31 @@ template <> struct StageCfg<PK_H16, 1> { static constexpr bool ONE = true, SA = 
 template <> struct StageCfg<PK_H16, 2> { static constexpr bool ONE = true, SA = false, SC = true, XC = true, ACC64 = false; static constexpr int FS = 7, FX = 1, NW = 8, KS = 128; using Out = float; };
 template <> struct StageCfg<PK_H16, 3> { static constexpr bool ONE = false, SA = true, SC = false, XC = true, ACC64 = true; static constexpr int FS = 7, FX = 1, NW = 4, KS = 128; using Out = double; };
 
+// The configuration with the shared tile's height set to FSN 16-row fragments
+// (FSN = 0: the table's default).  Stages 1-3 share an operand with N rows
+// (G_b, Gbar_b, V'), so their tile follows the basis size (16 ceil(N/16)
+// rows instead of always 112): at N = 64 a 112-row tile would spend 3/7 of its
+// products on padding.  Stage 0 shares the 2 S N rows of the stacked G.
+template <int PK, int STAGE, int FSN>
+struct StageCfgN : StageCfg<PK, STAGE> {
+  static constexpr int FS = (STAGE == 0 || FSN == 0) ? StageCfg<PK, STAGE>::FS : FSN;
+};
+
+// Tile height (16-row fragments) of stages 1-3 for basis size N: the smallest
+// of 2, 4, 6, 7, 8 that covers N (the instantiated variants).
+__host__ __device__ inline int stage_fs(int N) {
+  return N <= 32 ? 2 : N <= 64 ? 4 : N <= 96 ? 6 : N <= 112 ? 7 : 8;
+}
+
 // Launch geometry of one stage: grid = (tiles_s * npersist, nbatch, nz).
 struct StageGeom {
   int tiles_s, tiles_x, npersist, nbatch, nz;
   __host__ __device__ long long blocks() const { return (long long)tiles_s * npersist * nbatch * nz; }
 };
 
-template <int PK, int STAGE>
+template <int PK, int STAGE, int FSN = 0>
 __host__ __device__ inline StageGeom stage_geom(StreamArgs& g, int nbatch, int persist_target) {
-  using C = StageCfg<PK, STAGE>;
+  using C = StageCfgN<PK, STAGE, FSN>;
   constexpr int SR = 16 * C::FS;
   constexpr int XT = 16 * C::FX * C::NW;
   const int slim = C::SA ? g.M : g.N, xlim = C::SA ? g.N : g.M;
@@ -131,9 +147,9 @@ __host__ __device__ inline StageGeom stage_geom(StreamArgs& g, int nbatch, int p
   return q;
 }
 
-template <int PK, int STAGE>
+template <int PK, int STAGE, int FSN = 0>
 __device__ __forceinline__ void run_stage_block(const StreamArgs& g, const StageGeom& q, long long local) {
-  using C = StageCfg<PK, STAGE>;
+  using C = StageCfgN<PK, STAGE, FSN>;
   const long long gx = (long long)q.tiles_s * q.npersist;
   const int bx = (int)(local % gx);
   const long long rest = local / gx;
@@ -146,10 +162,11 @@ __device__ __forceinline__ void run_stage_block(const StreamArgs& g, const Stage
                                                                                                  q.npersist);
 }
 
-template <int PK, int STAGE>
+template <int PK, int STAGE, int FSN = 0>
 __global__ void __launch_bounds__((64 * StageCfg<PK, STAGE>::NW)) k_stage(const StreamArgs g, const StageGeom q) {
   const long long gx = (long long)q.tiles_s * q.npersist;
-  run_stage_block<PK, STAGE>(g, q, (long long)blockIdx.x + gx * ((long long)blockIdx.y + (long long)q.nbatch * blockIdx.z));
+  run_stage_block<PK, STAGE, FSN>(g, q,
+                                  (long long)blockIdx.x + gx * ((long long)blockIdx.y + (long long)q.nbatch * blockIdx.z));
 }
 
 // ---------------------------------------------------------------------------
@@ -165,7 +182,9 @@ struct GroupTable {
   long long off[MAX_GROUP + 1];
 };
 
-template <int PK, int STAGE>
+// All members of one grouped launch share the tile height FSN (the batched
+// path groups systems by ceil(N/16)).
+template <int PK, int STAGE, int FSN = 0>
 __global__ void __launch_bounds__((64 * StageCfg<PK, STAGE>::NW))
 k_stage_group(const ChainRefs* __restrict__ refs, const GroupTable t) {
   const long long b = blockIdx.x;
@@ -174,8 +193,8 @@ k_stage_group(const ChainRefs* __restrict__ refs, const GroupTable t) {
   const ChainRefs r = refs[i];
   int nbatch;
   StreamArgs g = stage_args(STAGE, r, nbatch);
-  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, t.persist[i]);
-  run_stage_block<PK, STAGE>(g, q, b - t.off[i]);
+  const StageGeom q = stage_geom<PK, STAGE, FSN>(g, nbatch, t.persist[i]);
+  run_stage_block<PK, STAGE, FSN>(g, q, b - t.off[i]);
 }
 
 // Write a table of chain refs into device memory (the table travels as kernel

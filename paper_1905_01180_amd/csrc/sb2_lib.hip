@@ -464,16 +464,32 @@ ChainRefs chain_refs(int prec, int N, int ns, const ChainPlan& p, void* ws, void
   return r;
 }
 
-template <int PK, int STAGE>
-hipError_t launch_stage(const ChainRefs& r, hipStream_t st) {
+template <int PK, int STAGE, int FSN>
+hipError_t launch_stage_fs(const ChainRefs& r, hipStream_t st) {
   int nbatch;
   StreamArgs g = stage_args(STAGE, r, nbatch);
-  const StageGeom q = stage_geom<PK, STAGE>(g, nbatch, tune_of(r.N, r.prec).persist);
+  const StageGeom q = stage_geom<PK, STAGE, FSN>(g, nbatch, tune_of(r.N, r.prec).persist);
   const long long gx = (long long)q.tiles_s * q.npersist;
   dim3 grid((unsigned)gx, (unsigned)q.nbatch, (unsigned)q.nz);
   StageTimer tm(STAGE, st);
-  hipLaunchKernelGGL((k_stage<PK, STAGE>), grid, dim3(64 * StageCfg<PK, STAGE>::NW), 0, st, g, q);
+  hipLaunchKernelGGL((k_stage<PK, STAGE, FSN>), grid, dim3(64 * StageCfg<PK, STAGE>::NW), 0, st, g, q);
   return hipGetLastError();
+}
+
+// Stages 1-3: the shared tile's height follows N (stage_fs)
+template <int PK, int STAGE>
+hipError_t launch_stage(const ChainRefs& r, hipStream_t st) {
+  if constexpr (STAGE == 0) {
+    return launch_stage_fs<PK, 0, 0>(r, st);
+  } else {
+    switch (stage_fs(r.N)) {
+      case 2: return launch_stage_fs<PK, STAGE, 2>(r, st);
+      case 4: return launch_stage_fs<PK, STAGE, 4>(r, st);
+      case 6: return launch_stage_fs<PK, STAGE, 6>(r, st);
+      case 7: return launch_stage_fs<PK, STAGE, 7>(r, st);
+      default: return launch_stage_fs<PK, STAGE, 8>(r, st);
+    }
+  }
 }
 
 template <int NT>
@@ -729,21 +745,43 @@ BwdPlan bwd_plan(int N, int T) {
   return b;
 }
 
-// float64 GEMM configurations of the adjoint
-hipError_t zg_m(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 1, 4, 7, 1, true, true, false>(g, nb, s); }
-hipError_t zg_n(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 4, 1, 1, 7, true, true, false>(g, nb, s); }
-hipError_t zg_n_rc(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 4, 1, 1, 7, false, true, false>(g, nb, s); }
-hipError_t zg_m_cr(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 1, 4, 7, 1, true, false, false>(g, nb, s); }
-hipError_t zg_m_k2(GemmArgs g, int nb, hipStream_t s) {
-  constexpr int BM = 112, BN = 64;
+// float64 GEMM configurations of the adjoint; F = 16-wide fragments per wave
+// along the N-sized side (rows for zg_m*, columns for zg_n*), chosen from N so
+// that the tile covers N with little padding (4 up to N = 64, 7 up to 112, 8)
+template <int F>
+hipError_t zg_m_f(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 1, 4, F, 1, true, true, false>(g, nb, s); }
+template <int F>
+hipError_t zg_n_f(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 4, 1, 1, F, true, true, false>(g, nb, s); }
+template <int F>
+hipError_t zg_n_rc_f(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 4, 1, 1, F, false, true, false>(g, nb, s); }
+template <int F>
+hipError_t zg_m_cr_f(GemmArgs g, int nb, hipStream_t s) { return launch_f<double, double, 1, 4, F, 1, true, false, false>(g, nb, s); }
+template <int F>
+hipError_t zg_m_k2_f(GemmArgs g, int nb, hipStream_t s) {
+  constexpr int BM = 16 * F, BN = 64;
   if (g.kchunk <= 0) g.kchunk = g.K;
   g.tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int nz = (g.K + g.kchunk - 1) / g.kchunk;
   dim3 grid(g.tiles_m * tiles_n, nb, nz);
-  hipLaunchKernelGGL((k_gemm<double, double, 1, 4, 7, 1, true, true, false, true>), grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL((k_gemm<double, double, 1, 4, F, 1, true, true, false, true>), grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
+inline int bwd_f(int N) { return N <= 64 ? 4 : N <= 112 ? 7 : 8; }
+#define BWD_DISPATCH(name)                                              \
+  hipError_t name(GemmArgs g, int nb, hipStream_t s, int N) {           \
+    switch (bwd_f(N)) {                                                 \
+      case 4: return name##_f<4>(g, nb, s);                             \
+      case 7: return name##_f<7>(g, nb, s);                             \
+      default: return name##_f<8>(g, nb, s);                            \
+    }                                                                   \
+  }
+BWD_DISPATCH(zg_m)
+BWD_DISPATCH(zg_n)
+BWD_DISPATCH(zg_n_rc)
+BWD_DISPATCH(zg_m_cr)
+BWD_DISPATCH(zg_m_k2)
+#undef BWD_DISPATCH
 
 #define BW_TRY(expr)                          \
   do {                                        \
@@ -815,28 +853,28 @@ hipError_t collision_backward(int N, int T, const double* v, const void* h, cons
     g.A = Vp; g.sAm = 1; g.sAk = ch.KpV;
     g.B = gSs; g.sBk = N; g.sBn = 1; g.sBbh = n2;
     g.C = GC; g.Mlo = N; g.sCmh = n2; g.sCm = 1; g.sCn = N; g.sCbh = n4;
-    BW_TRY(zg_n_rc(g, ns, s));
+    BW_TRY(zg_n_rc(g, ns, s, N));
     // gVp[i][col] (+)= Re sum_{(b,j)} gS_b[i][j] conj(C_b[j][col])
     g = gdef();
     g.M = N; g.N = (int)n3; g.K = ns * N;
     g.A = gSt; g.sAm = (i64)ns * N; g.sAk = 1;
     g.B = C3; g.sBk = n3; g.sBn = 1; g.conjB = 1;
     g.C = gVp; g.sCm = n3; g.sCn = 1; g.out_real = 1; g.beta1 = first ? 0 : 1;
-    BW_TRY(zg_m(g, 1, s));
+    BW_TRY(zg_m(g, 1, s, N));
     // R3 adjoint: gB[b][(n,p,j)][s] = sum_r gCt[b][(n,p,j)][r] conj(GbT[b][r][s])
     g = gdef();
     g.M = (int)n3; g.N = N; g.K = N;
     g.A = GC; g.sAm = N; g.sAk = 1; g.sAbh = n4;
     g.B = GbT; g.sBk = N; g.sBn = 1; g.sBbh = n2; g.conjB = 1;
     g.C = GB; g.sCm = N; g.sCn = 1; g.sCbh = n4;
-    BW_TRY(zg_n(g, ns, s));
+    BW_TRY(zg_n(g, ns, s, N));
     // gGbar_b[s][r] = sum_{(n,p,j)} conj(B_b[(n,p,j)][s]) gCt_b[(n,p,j)][r]   (split-K)
     g = gdef();
     g.M = N; g.N = N; g.K = (int)n3; g.kchunk = b.kchunk2;
     g.A = B2; g.sAm = 1; g.sAk = N; g.sAbh = n4; g.conjA = 1;
     g.B = GC; g.sBk = N; g.sBn = 1; g.sBbh = n4;
     g.C = part2; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.sCz = (i64)ns * n2;
-    BW_TRY(zg_m(g, ns, s));
+    BW_TRY(zg_m(g, ns, s, N));
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks((long long)ns * n2, 256)), dim3(256), 0, s, (i64)ns * n2,
                        b.nz2, part2, gGbs, 0);
     BW_TRY(hipGetLastError());
@@ -846,14 +884,14 @@ hipError_t collision_backward(int N, int T, const double* v, const void* h, cons
     g.A = GB; g.sAm = 1; g.sAk = n2; g.sAbh = n4; g.sAbl = n3;
     g.B = Gs; g.sBk = N; g.sBn = 1; g.sBbh = n2; g.sBbl = 0; g.conjB = 1;
     g.C = GC; g.sCm = N; g.sCn = 1; g.sCbh = n4; g.sCbl = n3;
-    BW_TRY(zg_n(g, ns * N, s));
+    BW_TRY(zg_n(g, ns * N, s, N));
     // gG_b[p][q] = sum_{(n,x)} gB[b][n][p][x] conj(A'[b][n][x][q])   (second G slot, split-K)
     g = gdef();
     g.M = N; g.N = N; g.K = (int)n3; g.kchunk = b.kchunk2; g.Klo = (int)n2;
     g.A = GB; g.sAm = n2; g.sAk = 1; g.sAkh = n3; g.sAbh = n4;
     g.B = A1; g.sBk = N; g.sBkh = n3; g.sBn = 1; g.sBbh = n4; g.conjB = 1;
     g.C = part2; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.sCz = (i64)ns * n2;
-    BW_TRY(zg_m_k2(g, ns, s));
+    BW_TRY(zg_m_k2(g, ns, s, N));
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks((long long)ns * n2, 256)), dim3(256), 0, s, (i64)ns * n2,
                        b.nz2, part2, gGs, 0);
     BW_TRY(hipGetLastError());
@@ -863,7 +901,7 @@ hipError_t collision_backward(int N, int T, const double* v, const void* h, cons
     g.A = GC; g.sAm = n3; g.sAk = 1; g.sAbh = n4;
     g.B = WT; g.sBk = ch.KpW; g.sBn = 1;
     g.C = part2; g.sCm = N; g.sCn = 1; g.sCbh = n2; g.sCz = (i64)ns * n2;
-    BW_TRY(zg_m_cr(g, ns, s));
+    BW_TRY(zg_m_cr(g, ns, s, N));
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks((long long)ns * n2, 256)), dim3(256), 0, s, (i64)ns * n2,
                        b.nz2, part2, gGs, 1);
     BW_TRY(hipGetLastError());
@@ -873,7 +911,7 @@ hipError_t collision_backward(int N, int T, const double* v, const void* h, cons
     g.A = GC; g.sAm = 1; g.sAk = n3;
     g.B = Gs; g.sBk = N; g.sBn = 1; g.conjB = 1;
     g.C = gWT; g.sCm = N; g.sCn = 1; g.out_real = 1; g.beta1 = first ? 0 : 1;
-    BW_TRY(zg_n(g, 1, s));
+    BW_TRY(zg_n(g, 1, s, N));
     hipLaunchKernelGGL(k_scatter_gg, dim3(blocks((long long)np * n2, 256)), dim3(256), 0, s, N, np, gGs, gGbs,
                        gGl + ko, gGg + ko, gGlb + ko, gGgb + ko);
     BW_TRY(hipGetLastError());
@@ -1031,9 +1069,9 @@ BatchPlan batch_plan(int nsys, const sb2_system* sys, int prec) {
 
 // share[i]: member i's part of the launch's work; the workgroup target of the
 // single-slab stages is divided among the members in that proportion.
-template <int PK, int STAGE>
-hipError_t launch_group(const std::vector<ChainRefs>& refs, const std::vector<double>& share, const ChainRefs* d_refs,
-                        hipStream_t st) {
+template <int PK, int STAGE, int FSN>
+hipError_t launch_group_fs(const std::vector<ChainRefs>& refs, const std::vector<double>& share,
+                           const ChainRefs* d_refs, hipStream_t st) {
   GroupTable t;
   t.count = (int)refs.size();
   long long off = 0;
@@ -1043,14 +1081,33 @@ hipError_t launch_group(const std::vector<ChainRefs>& refs, const std::vector<do
     t.persist[i] = want < 1.0 ? 1 : (int)want;
     int nbatch;
     StreamArgs g = stage_args(STAGE, refs[i], nbatch);
-    off += stage_geom<PK, STAGE>(g, nbatch, t.persist[i]).blocks();
+    off += stage_geom<PK, STAGE, FSN>(g, nbatch, t.persist[i]).blocks();
   }
   t.off[t.count] = off;
   if (off <= 0) return hipSuccess;
   StageTimer tm(STAGE, st);
-  hipLaunchKernelGGL((k_stage_group<PK, STAGE>), dim3((unsigned)off), dim3(64 * StageCfg<PK, STAGE>::NW), 0, st,
-                     d_refs, t);
+  hipLaunchKernelGGL((k_stage_group<PK, STAGE, FSN>), dim3((unsigned)off), dim3(64 * StageCfg<PK, STAGE>::NW), 0,
+                     st, d_refs, t);
   return hipGetLastError();
+}
+
+// the members of a group share ceil(N/16), hence the tile height of stages 1-3
+template <int PK, int STAGE>
+hipError_t launch_group(const std::vector<ChainRefs>& refs, const std::vector<double>& share, const ChainRefs* d_refs,
+                        hipStream_t st) {
+  int nmax = 1;
+  for (const ChainRefs& r : refs) nmax = std::max(nmax, r.N);
+  if constexpr (STAGE == 0) {
+    return launch_group_fs<PK, 0, 0>(refs, share, d_refs, st);
+  } else {
+    switch (stage_fs(nmax)) {
+      case 2: return launch_group_fs<PK, STAGE, 2>(refs, share, d_refs, st);
+      case 4: return launch_group_fs<PK, STAGE, 4>(refs, share, d_refs, st);
+      case 6: return launch_group_fs<PK, STAGE, 6>(refs, share, d_refs, st);
+      case 7: return launch_group_fs<PK, STAGE, 7>(refs, share, d_refs, st);
+      default: return launch_group_fs<PK, STAGE, 8>(refs, share, d_refs, st);
+    }
+  }
 }
 
 template <int PK>
