@@ -260,15 +260,30 @@ k_gemm(const GemmArgs g) {
   auto gload = [&](int k0) {
     const int klim = kend - k0;
     if constexpr (K2) {
-      // two-level K: element k = kh Klo + kl at kh s*kh + kl s*k
-      ra.load(Ab, [&](int r, int c) {
-        const int kk = k0 + c, kh = kk / g.Klo;
-        return (i64)r * g.sAm + (i64)kh * g.sAkh + (i64)(kk - kh * g.Klo) * g.sAk;
-      }, mlim, klim, a_cfast, tid);
-      rb.load(Bb, [&](int r, int c) {
-        const int kk = k0 + r, kh = kk / g.Klo;
-        return (i64)kh * g.sBkh + (i64)(kk - kh * g.Klo) * g.sBk + (i64)c * g.sBn;
-      }, klim, nlim, b_cfast, tid);
+      // two-level K: element k = kh Klo + kl at kh s*kh + kl s*k.  One division
+      // per slab when BK <= Klo: the slab's BK consecutive k cross at most one
+      // multiple of Klo, so each element's (kh, kl) is (kh0, kl0 + c) or
+      // (kh0 + 1, kl0 + c - Klo).
+      if (g.Klo >= BK) {                               // uniform
+        const int kh0 = k0 / g.Klo, kl0 = k0 - kh0 * g.Klo;
+        const i64 a0 = (i64)kh0 * g.sAkh + (i64)kl0 * g.sAk, b0 = (i64)kh0 * g.sBkh + (i64)kl0 * g.sBk;
+        const i64 a_wrap = g.sAkh - (i64)g.Klo * g.sAk, b_wrap = g.sBkh - (i64)g.Klo * g.sBk;
+        ra.load(Ab, [&](int r, int c) {
+          return (i64)r * g.sAm + a0 + (i64)c * g.sAk + (kl0 + c >= g.Klo ? a_wrap : 0);
+        }, mlim, klim, a_cfast, tid);
+        rb.load(Bb, [&](int r, int c) {
+          return b0 + (i64)r * g.sBk + (kl0 + r >= g.Klo ? b_wrap : 0) + (i64)c * g.sBn;
+        }, klim, nlim, b_cfast, tid);
+      } else {                                         // Klo < BK (N < 4): a division per element
+        ra.load(Ab, [&](int r, int c) {
+          const int kk = k0 + c, kh = kk / g.Klo;
+          return (i64)r * g.sAm + (i64)kh * g.sAkh + (i64)(kk - kh * g.Klo) * g.sAk;
+        }, mlim, klim, a_cfast, tid);
+        rb.load(Bb, [&](int r, int c) {
+          const int kk = k0 + r, kh = kk / g.Klo;
+          return (i64)kh * g.sBkh + (i64)(kk - kh * g.Klo) * g.sBk + (i64)c * g.sBn;
+        }, klim, nlim, b_cfast, tid);
+      }
     } else {
       ra.load(Ab + PA * (i64)k0 * g.sAk, g.sAm, g.sAk, mlim, klim, a_cfast, tid);
       rb.load(Bb + PB * (i64)k0 * g.sBk, g.sBk, g.sBn, klim, nlim, b_cfast, tid);

@@ -714,9 +714,12 @@ BwdPlan bwd_plan(int N, int T) {
   b.ch = chain_plan(N, T, SB2_FP64, o, (int)S);
   o = b.ch.end;
   const size_t ns = 2 * S;
-  // split-K of the three K = N^3 reductions: >= ~1024 workgroups
-  const long long per_z = 2LL * (long long)ns;
-  long long nz = (1024 + per_z - 1) / per_z;
+  // split-K of the three K = N^3 reductions: >= ~2048 workgroups (N x N
+  // output tiles of the adjoint's products: 16 F rows, F as chosen by bwd_f,
+  // by 64 columns)
+  const int bm = 16 * (N <= 64 ? 4 : N <= 112 ? 7 : 8);
+  const long long per_z = (long long)ns * ((N + bm - 1) / bm) * ((N + 63) / 64);
+  long long nz = (2048 + per_z - 1) / per_z;
   long long kc = ((long long)n3 + nz - 1) / nz;
   kc = (kc + 15) / 16 * 16;
   b.kchunk2 = (int)kc;
