@@ -164,3 +164,20 @@ def test_propagation_graph_replay_matches_eager():
         for a, b in zip((rho, u, ih), eager):
             assert torch.equal(a, b), rep
         _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between replays
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+def test_collision_with_damped_propagators(prec):
+    # GKBA with a correlated (non-unitary) propagator, e.g. a quasiparticle
+    # propagator with a damping width gamma: U(t, t_k) = exp(-(i h + gamma)(t - t_k)).
+    # Nothing in the path assumes unitarity; the oracle builds the same GKBA
+    # functions from the supplied propagators.
+    import scipy.linalg
+    n, t, gamma = 14, 6, 0.3
+    h, v, _ = _system(n, 77)
+    rho = gen.rho_history(n, t, DT, gen.rng(70, 77, 1))
+    u = np.stack([scipy.linalg.expm(-(1j * h + gamma * np.eye(n)) * (t - k) * DT) for k in range(t)])
+    ref = d.collision_from_propagators(v, u, rho, DT)
+    got = _lib.sb2_collision_prop(_dev(v), _dev(u), _dev(rho), DT, prec).cpu().numpy()
+    print(f"damped propagators N={n} T={t} {prec}: rel {relf(got, ref):.2e}", flush=True)
+    assert relf(got, ref) < TOL[prec]
