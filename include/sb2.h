@@ -270,6 +270,25 @@ int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, cons
                                 void* U_hist, void* I_hist, const double* lambda, double dt, int flags, int prec,
                                 void* ws, size_t ws_bytes, void* stream);
 
+/* sb2_gkba_propagate_qp -- sb2_gkba_propagate with correlated (quasiparticle)
+ * propagators in the GKBA, the extension the Conclusion names beside GW,
+ * T-matrix and initial correlations: the propagators of Eq. 11 that build the
+ * two-time functions of Eq. 10 are generated by h_HF(t) + sigma_qp instead of
+ * h_HF(t), with sigma_qp a constant N x N complex matrix (device, row-major,
+ * caller-owned), for example -i Gamma/2 with Gamma Hermitian positive
+ * semidefinite (a quasiparticle damping); a Hermitian part shifts the
+ * quasiparticle energies.  Per step n:
+ *   U_step(n)   = exp(-i h_HF(t_n) dt)               advances the density (Eq. 8),
+ *   Uqp_step(n) = exp(-i (h_HF(t_n) + sigma_qp) dt)  advances the history,
+ *   U_hist[k]   = U_qp(t_n, t_k) = Uqp_step(n-1) ... Uqp_step(k),
+ * and I_n is the collision integral of these propagators (sb2_collision_prop).
+ * sigma_qp = 0 reproduces sb2_gkba_propagate bit for bit.  Everything else,
+ * the workspace size and the errors as sb2_gkba_propagate; SB2_EINVAL for
+ * sigma_qp == NULL.                                                         */
+int sb2_gkba_propagate_qp(int N, int n0, int nsteps, const double* v, const void* h, const void* sigma_qp,
+                          void* rho_hist, void* U_hist, void* I_hist, double dt, int flags, int prec, void* ws,
+                          size_t ws_bytes, void* stream);
+
 /* sb2_gkba_propagate_vertex -- sb2_gkba_propagate for a special vertex of
  * Sec. III (Sec. IV runs its chains this way), float64 throughout.  Per step
  * n exactly the scheme of sb2_gkba_propagate, with

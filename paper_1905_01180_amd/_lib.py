@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_collision_vertex.argtypes = [_i, _i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _sz, _vp]
         L.sb2_gkba_propagate_vertex.restype = _i
         L.sb2_gkba_propagate_vertex.argtypes = [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
+        L.sb2_gkba_propagate_qp.restype = _i
+        L.sb2_gkba_propagate_qp.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         L.sb2_gkba_propagate_switched.restype = _i
         L.sb2_gkba_propagate_switched.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz,
                                                   _vp]
@@ -312,13 +314,15 @@ def sb2_collision_vertex(vertex: str, param: torch.Tensor, h: torch.Tensor, rho_
 
 
 def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, prec="fp64", hf: bool = True,
-                       collision: bool = True, i_hist=None, switch=None):
+                       collision: bool = True, i_hist=None, switch=None, sigma_qp=None):
     """Advance the propagation state in place from step n0 to n0 + nsteps.
 
     rho_hist (C, N, N) with C >= n0 + nsteps + 1, u_hist and i_hist (C', N, N)
     with C' >= n0 + nsteps (i_hist optional); all complex128 on the device.
     switch: optional device float64 coupling history lambda(t_m) (the
     interaction is lambda(t) v; sb2_gkba_propagate_switched).
+    sigma_qp: optional constant (N, N) complex128 correction of the GKBA
+    propagators (sb2_gkba_propagate_qp); not combined with switch.
     """
     n = h.shape[0]
     _check(v, "v", torch.float64, (n, n, n, n))
@@ -334,6 +338,14 @@ def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, 
     p = _prec(prec)
     ws = workspace(sb2_workspace_size("propagate", n, n0 + nsteps, p), v.device)
     flags = (PROP_HF if hf else 0) | (PROP_COLLISION if collision else 0)
+    if switch is not None and sigma_qp is not None:
+        raise ValueError("switch and sigma_qp are separate entry points; pass one of them")
+    if sigma_qp is not None:
+        _check(sigma_qp, "sigma_qp", torch.complex128, (n, n))
+        _call("sb2_gkba_propagate_qp", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), sigma_qp.data_ptr(),
+              rho_hist.data_ptr(), u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None,
+              float(dt), flags, p, ws.data_ptr(), ws.numel(), _stream(v.device))
+        return
     if switch is not None:
         # time-dependent coupling: switch[m] = lambda(t_m), m < n0 + nsteps (device float64)
         _check(switch, "switch", torch.float64, (switch.shape[0],))

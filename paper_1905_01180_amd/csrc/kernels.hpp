@@ -652,6 +652,12 @@ __global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
   if (e < n) x[e] = cmul(mk(a, b), x[e]);
 }
 
+// out <- a + b (complex)
+__global__ void k_add_c(i64 n, const cplx* __restrict__ a, const cplx* __restrict__ b, cplx* __restrict__ out) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = a[e] + b[e];
+}
+
 // Strided complex copy, used to lay out small operands.
 __global__ void k_copy(i64 n, const cplx* __restrict__ src, cplx* __restrict__ dst) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;

@@ -282,7 +282,7 @@ VertPlan vert_plan(int N, int T, int vertex) {
 // grows with T; vertex != 0: the special-vertex plan) followed by the step's
 // own N x N matrices and the staging area of the propagator-history update.
 struct PropPlan {
-  size_t heff, ustep, I, T1, ex1, ex2, tmp, end;
+  size_t heff, ustep, hqp, uqp, I, T1, ex1, ex2, tmp, end;
 };
 PropPlan prop_plan(int N, int n_end, int prec, int vertex = 0) {
   PropPlan p;
@@ -291,6 +291,8 @@ PropPlan prop_plan(int N, int n_end, int prec, int vertex = 0) {
   if (n_end >= 2) o = al(vertex ? vert_plan(N, n_end - 1, vertex).end : coll_plan(N, n_end - 1, prec).end);
   p.heff = o; o += m;
   p.ustep = o; o += m;
+  p.hqp = o; o += m;
+  p.uqp = o; o += m;
   p.I = o; o += m;
   p.T1 = o; o += m;
   p.ex1 = o; o += m;
@@ -1700,9 +1702,13 @@ hipError_t collision_vertex_core(int N, int T, int vertex, const double* vparam,
 // h_HF from hf(rho_n, heff), U_step = exp(-i h_HF dt), I_n from coll(n, U, I)
 // over the past times t_0 .. t_{n-1} (I_0 = 0), the exponential-Euler density
 // step and the propagator-history update.  hf and coll enqueue their work.
+// sqp (optional): a constant correction of the GKBA propagator, whose history
+// is then advanced by exp(-i (h_HF + sqp) dt) while the density step keeps
+// U_step.
 template <class HF, class COLL>
 hipError_t propagate_steps(int N, int n0, int n_end, void* rho_hist, void* U_hist, void* I_hist, double dt,
-                           int flags, const PropPlan& p, void* ws, hipStream_t s, HF&& hf, COLL&& coll) {
+                           int flags, const PropPlan& p, void* ws, hipStream_t s, HF&& hf, COLL&& coll,
+                           const cplx* sqp = nullptr) {
   const i64 nn = (i64)N * N;
   const size_t mb = (size_t)nn * C128;
   cplx* rho = reinterpret_cast<cplx*>(rho_hist);
@@ -1714,6 +1720,8 @@ hipError_t propagate_steps(int N, int n0, int n_end, void* rho_hist, void* U_his
   cplx* ex1 = reinterpret_cast<cplx*>(at(ws, p.ex1));
   cplx* ex2 = reinterpret_cast<cplx*>(at(ws, p.ex2));
   cplx* tmp = reinterpret_cast<cplx*>(at(ws, p.tmp));
+  // propagator of the GKBA history: U_step itself, or the corrected step
+  cplx* uhist = ustep;
   hipError_t e;
   for (int n = n0; n < n_end; ++n) {
     cplx* rho_n = rho + (i64)n * nn;
@@ -1721,6 +1729,14 @@ hipError_t propagate_steps(int N, int n0, int n_end, void* rho_hist, void* U_his
     if ((e = hf(rho_n, heff)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, heff, 0.0, -dt, ustep, ex1, ex2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (sqp) {
+      cplx* hqp = reinterpret_cast<cplx*>(at(ws, p.hqp));
+      uhist = reinterpret_cast<cplx*>(at(ws, p.uqp));
+      hipLaunchKernelGGL(k_add_c, dim3(blocks(nn, 256)), dim3(256), 0, s, nn, heff, sqp, hqp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, hqp, 0.0, -dt, uhist, ex1, ex2);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // I_ns(t_n) over the past times t_0 .. t_{n-1} (Eq. 9)
     if ((flags & SB2_PROP_COLLISION) && n > 0) {
       if ((e = coll(n, U, rho, I)) != hipSuccess) return e;
@@ -1748,16 +1764,17 @@ hipError_t propagate_steps(int N, int n0, int n_end, void* rho_hist, void* U_his
     hipLaunchKernelGGL(k_rho_finish, dim3(blocks(nn, 256)), dim3(256), 0, s, N, ex1, I, dt, rho_n + nn);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // U(t_{n+1}, t_k) = U_step U(t_n, t_k) for k < n, U(t_{n+1}, t_n) = U_step
+    // (with the corrected step when sqp is given)
     if (n > 0) {
       g = gdef();
       g.M = N; g.N = N; g.K = N;
-      g.A = ustep; g.sAm = N; g.sAk = 1; g.sAbh = 0;
+      g.A = uhist; g.sAm = N; g.sAk = 1; g.sAbh = 0;
       g.B = U; g.sBk = N; g.sBn = 1; g.sBbh = nn;
       g.C = tmp; g.sCm = N; g.sCn = 1; g.sCbh = nn;
       if ((e = zgemm(g, n, s)) != hipSuccess) return e;
       if ((e = hipMemcpyAsync(U, tmp, (size_t)n * mb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
     }
-    if ((e = hipMemcpyAsync(U + (i64)n * nn, ustep, mb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(U + (i64)n * nn, uhist, mb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1810,7 +1827,7 @@ namespace {
 // self-energy Sigma(t_n, t_k) lambda(t_n) lambda(t_k)).
 int propagate_general(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* U_hist,
                       void* I_hist, const double* lam, double dt, int flags, int prec, void* ws, size_t ws_bytes,
-                      void* stream) {
+                      void* stream, const void* sqp = nullptr) {
   if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
   if (!v || !h || !rho_hist || !U_hist || !ws || !finite_pos(dt)) return SB2_EINVAL;
   if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
@@ -1820,7 +1837,7 @@ int propagate_general(int N, int n0, int nsteps, const double* v, const void* h,
   if (ws_bytes < p.end) return SB2_EWORKSPACE;
   SB2_ENTRY();
   SB2_CHECKS(ws, N, {2, v, (i64)N * N * N * N}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, U_hist, (i64)n0 * N * N},
-             {2, lam, lam ? (i64)n_end : 0});
+             {2, lam, lam ? (i64)n_end : 0}, {1, sqp, sqp ? (i64)N * N : 0});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int now = 0;
   auto hf = [&](const cplx* rho_n, cplx* heff) {
@@ -1833,7 +1850,8 @@ int propagate_general(int N, int n0, int nsteps, const double* v, const void* h,
     const CollPlan c = coll_plan(N, n, prec);
     return collision_core(N, n, v, U, rho, dt, I, nullptr, prec, c, ws, s, false, lam, n);
   };
-  SB2_TRY(propagate_steps(N, n0, n_end, rho_hist, U_hist, I_hist, dt, flags, p, ws, s, hf, coll));
+  SB2_TRY(propagate_steps(N, n0, n_end, rho_hist, U_hist, I_hist, dt, flags, p, ws, s, hf, coll,
+                          reinterpret_cast<const cplx*>(sqp)));
   return SB2_OK;
 }
 }  // namespace
@@ -1852,6 +1870,14 @@ int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, cons
   if (!lambda) return SB2_EINVAL;
   return propagate_general(N, n0, nsteps, v, h, rho_hist, U_hist, I_hist, lambda, dt, flags, prec, ws, ws_bytes,
                            stream);
+}
+
+int sb2_gkba_propagate_qp(int N, int n0, int nsteps, const double* v, const void* h, const void* sigma_qp,
+                          void* rho_hist, void* U_hist, void* I_hist, double dt, int flags, int prec, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!sigma_qp) return SB2_EINVAL;
+  return propagate_general(N, n0, nsteps, v, h, rho_hist, U_hist, I_hist, nullptr, dt, flags, prec, ws, ws_bytes,
+                           stream, sigma_qp);
 }
 
 int sb2_gkba_propagate_vertex(int N, int n0, int nsteps, int vertex, const double* vparam, const void* h,

@@ -151,3 +151,13 @@ def test_switched_propagation_arguments(L):
     assert p(0, 0, 2, FAKE, FAKE, FAKE, FAKE, None, FAKE, 0.05, 3, 0, FAKE, BIG, None) == -2
     assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, None, FAKE, 0.05, 3, 3, FAKE, BIG, None) == -5   # split BF16
     assert p(8, 0, 4, FAKE, FAKE, FAKE, FAKE, None, FAKE, 0.05, 3, 0, FAKE, 64, None) == -3
+
+
+def test_qp_propagation_arguments(L):
+    p = L.sb2_gkba_propagate_qp
+    # argument order: N, n0, nsteps, v, h, sigma_qp, rho, U, I, dt, flags, prec, ws, ws_bytes, stream
+    assert p(8, 0, 2, FAKE, FAKE, None, FAKE, FAKE, None, 0.05, 3, 0, FAKE, BIG, None) == -1   # no sigma_qp
+    assert p(0, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, 0, FAKE, BIG, None) == -2
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, 3, FAKE, BIG, None) == -5   # split BF16
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 8, 0, FAKE, BIG, None) == -1   # unknown flag
+    assert p(8, 0, 4, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, 0, FAKE, 64, None) == -3
