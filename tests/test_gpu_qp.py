@@ -81,3 +81,23 @@ def test_qp_limits():
     shift = run(v, h, rho0, steps, "fp64", 0.7 * np.eye(n, dtype=complex))
     assert max(relf(shift[0][m], plain[0][m]) for m in range(steps + 1)) < 1e-12
     assert max(relf(shift[2][m], plain[2][m]) for m in range(1, steps)) < 1e-11
+
+
+def test_qp_resume_is_bitwise():
+    # steps 0..5 then 6..10 in a second call (state kept in the caller's
+    # arrays) equals one call of 11 steps, bit for bit
+    from paper_1905_01180_amd import _lib
+    n, steps, split = 11, 11, 6
+    h, v, rho0 = _system(n, 3)
+    sq = _dev(_correction(n, 3))
+    print("case: qp resume N=11", flush=True)
+    one = run(v, h, rho0, steps, "fp16x3", _correction(n, 3))
+    rho = torch.zeros((steps + 1, n, n), dtype=torch.complex128, device=DEV)
+    u = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    ih = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    rho[0].copy_(_dev(rho0))
+    vd, hd = _dev(v), _dev(h)
+    _lib.sb2_gkba_propagate(vd, hd, rho, u, 0, split, DT, "fp16x3", i_hist=ih, sigma_qp=sq)
+    _lib.sb2_gkba_propagate(vd, hd, rho, u, split, steps - split, DT, "fp16x3", i_hist=ih, sigma_qp=sq)
+    two = (rho.cpu().numpy(), u.cpu().numpy(), ih.cpu().numpy())
+    assert all(np.array_equal(a, b) for a, b in zip(one, two))
