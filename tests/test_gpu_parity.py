@@ -129,3 +129,20 @@ def test_determinism():
         b = lib().sb2_collision(dev(s.v), dev(s.h), dev(s.rho_hist), s.dt, prec)
         torch.cuda.synchronize()
         assert torch.equal(a, b), prec
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+@pytest.mark.parametrize("filling", ["empty", "full"])
+def test_empty_or_full_band_gives_zero(filling, prec):
+    # no electron (rho = 0) or no hole (rho = 1): every self-energy and the
+    # collision integral vanish exactly, also through the split scales of
+    # all-zero operands; N = 100 takes the fused split-float16 chain
+    from paper_1905_01180_amd import _lib
+    n, t = 100, 3
+    s = gen.make_system(n, t, config_id=92, system_id=1)
+    rho = np.zeros((t, n, n), complex) if filling == "empty" else np.stack([np.eye(n, dtype=complex)] * t)
+    print(f"case: {filling} band N={n} T={t} {prec}", flush=True)
+    dev = torch.device("cuda:0")
+    i_out = _lib.sb2_collision(torch.from_numpy(s.v).to(dev), torch.from_numpy(s.h).to(dev),
+                               torch.from_numpy(np.ascontiguousarray(rho)).to(dev), s.dt, prec)
+    assert float(i_out.abs().max()) == 0.0

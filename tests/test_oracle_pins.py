@@ -87,6 +87,23 @@ def test_zero_interaction():
 
 # --- P3/P4: the paper's special vertices (Secs. III A, III B) ----------------
 
+@pytest.mark.parametrize("filling", ["empty", "full"])
+def test_empty_or_full_band_has_no_collisions(filling):
+    # rho = 0 makes G^<(t, t_k) and G^<(t_k, t) vanish, rho = 1 makes the
+    # greater functions vanish (Eq. 10); each self-energy of Eq. 13 holds a
+    # function of each kind (Sigma^< = S(G^<, G^>(t_k, t)), Sigma^> =
+    # S(G^>, G^<(t_k, t))), so with no electron or no hole there is no
+    # scattering: both self-energies and I are exactly zero for any v and h
+    n, t = 4, 5
+    s = gen.make_system(n, t, config_id=91, v_kind="generic")
+    rho = np.zeros((t, n, n), complex) if filling == "empty" else np.stack([np.eye(n, dtype=complex)] * t)
+    i_ns, sig = o.collision(s.v, s.h, rho, s.dt, return_sigma=True)
+    assert np.abs(i_ns).max() == 0.0
+    assert max(max(np.abs(sl).max(), np.abs(sg).max()) for sl, sg, _ in sig.values()) == 0.0
+    # a half-filled history scatters
+    assert np.abs(o.collision(s.v, s.h, s.rho_hist, s.dt)).max() > 1e-3
+
+
 def test_diagonal_basis_closed_form():
     g = np.random.default_rng(3)
     n = 5
