@@ -209,8 +209,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method shards over past times with one all-reduce of I per step; not built here).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the method would shard over past times with one all-reduce of I per step; not implemented).",
               file=sys.stderr)
         sys.exit(2)
 
