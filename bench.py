@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="measure the 32-system batch (N 24..96, T 64..512): one grouped call vs 32 single calls")
     ap.add_argument("--autotune", action="store_true", help="run sb2_autotune for the workload before timing")
+    ap.add_argument("--linear", action="store_true",
+                    help="with --propagate: the propagation with the sum over past times carried along (float64)")
     ap.add_argument("--propagate", action="store_true",
                     help="time whole GKBA propagation steps (HF + second-Born collisions) from a history of --t steps")
     ap.add_argument("--vertex", choices=["diagonal", "symmetric"],
@@ -227,6 +229,8 @@ def main():
     if args.batched:
         return batched(args, torch, _lib, gen, dev)
     if args.propagate:
+        if args.linear:
+            return propagate_linear(args, torch, _lib, gen, dev)
         return propagate(args, torch, _lib, gen, dev)
     if args.vertex:
         return vertex(args, torch, _lib, gen, dev)
@@ -620,6 +624,65 @@ def chain(args, torch, _lib, gen, dev):
         "site_occupation_final": [float(x) for x in occ[-1]],
         "paper_single_core_s": {"loop": loop_s, "contraction": contr_s,
                                 "hardware": "Intel Core i5-4460, 1 core (context, other machine)"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def propagate_linear(args, torch, _lib, gen, dev):
+    """Propagation with the sum over past times carried along
+    (sb2_gkba_propagate_linear, float64): --warmup then --steps steps from
+    t_0 (the cost of a step does not depend on the history length), and, for
+    comparison in the same run, --steps steps of the growing-history
+    propagation (sb2_gkba_propagate, float64) at history --t.
+    value = carried-sum propagation steps/s."""
+    import numpy as np
+    n, n0 = args.n, args.t
+    cid = 2 if (n, n0) == (100, 1000) else 99
+    s = gen.make_system(n, n0 + 1, config_id=cid)
+    v = torch.from_numpy(s.v).to(dev)
+    h = torch.from_numpy(s.h).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    # carried sum from t_0
+    total = args.warmup + args.steps
+    log(f"propagate --linear: N={n}, {total} steps from t_0, float64")
+    rho = torch.zeros((total + 1, n, n), dtype=torch.complex128, device=dev)
+    rho[0].copy_(torch.from_numpy(s.rho_hist[0]))
+    p = torch.zeros((n, n), dtype=torch.complex128, device=dev)
+    m = torch.zeros((n ** 4,), dtype=torch.complex128, device=dev)
+    if args.warmup:
+        _lib.sb2_gkba_propagate_linear(v, h, rho, p, m, 0, args.warmup, s.dt)
+    sec = timed(lambda: _lib.sb2_gkba_propagate_linear(v, h, rho, p, m, args.warmup, args.steps, s.dt)) / args.steps
+    flops = 84.0 * float(n) ** 5
+    tr = torch.diagonal(rho, dim1=1, dim2=2).sum(-1)
+    # growing-history steps at history n0 (synthetic state as in --propagate)
+    log(f"growing-history propagation at history {n0} for comparison")
+    rg = torch.zeros((n0 + args.steps + 1, n, n), dtype=torch.complex128, device=dev)
+    rg[: n0 + 1].copy_(torch.from_numpy(s.rho_hist))
+    u = torch.zeros((n0 + args.steps, n, n), dtype=torch.complex128, device=dev)
+    if n0 > 0:
+        u[:n0].copy_(torch.from_numpy(gen.unitary_path(s.h, s.dt * np.arange(n0, 0, -1))))
+    sec_g = timed(lambda: _lib.sb2_gkba_propagate(v, h, rg, u, n0, args.steps, s.dt, "fp64")) / args.steps
+    out = {
+        "metric": "GKBA propagation steps/s (N=%d, HF + second-Born collisions, sum over past times carried)" % n,
+        "value": 1.0 / sec, "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "GKBA propagation, N=%d basis, steps %d..%d from t_0, dt=%g" % (
+            n, args.warmup, total, s.dt), "N": n, "prec": "fp64"},
+        "flops_per_step": flops, "tflops_algorithmic": flops / sec / 1e12,
+        "trace_drift": float((tr - tr[0]).abs().max() / tr[0].abs()),
+        "growing_history": {"history": n0, "ms_per_step": 1e3 * sec_g,
+                            "flops_per_step": 48.0 * n0 * float(n) ** 5, "speedup": sec_g / sec},
     }
     print(json.dumps(out), flush=True)
 

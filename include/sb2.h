@@ -90,7 +90,8 @@ typedef enum {
   SB2_OP_COLLISION_DIAGONAL = 6,
   SB2_OP_COLLISION_SYMMETRIC = 7,
   SB2_OP_PROPAGATE_DIAGONAL = 8,
-  SB2_OP_PROPAGATE_SYMMETRIC = 9
+  SB2_OP_PROPAGATE_SYMMETRIC = 9,
+  SB2_OP_PROPAGATE_LINEAR = 10
 } sb2_op;
 
 /* Largest basis size and history length accepted. */
@@ -269,6 +270,36 @@ int sb2_gkba_propagate(int N, int n0, int nsteps, const double* v, const void* h
 int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist,
                                 void* U_hist, void* I_hist, const double* lambda, double dt, int flags, int prec,
                                 void* ws, size_t ws_bytes, void* stream);
+
+/* sb2_gkba_propagate_linear -- the propagation of sb2_gkba_propagate
+ * (HF propagators, float64 throughout) with the sum over past times of the
+ * collision integral (Eq. 9) carried along instead of recomputed.  The step
+ * propagators of Eq. 11 compose, U(t_n, t_k) = P_n P_k^dag with
+ * P_n = U(t_n, t_0), so each GKBA function of Eq. 10 is P_n (or P_n^dag)
+ * times a function of t_k alone, and P_n acts only on the three t-side legs
+ * of the interaction in Eq. 13:
+ *   I(t_n) = dt [sum_{(n,p,r)} vt_n[i][(n,p,r)] M_n[(n,p,r)][l]] P_n^dag,
+ *   vt_n[i][(n,p,r)] = sum v_{i r' p' n'} P_{n' n} P_{p' p} conj(P_{r' r}),
+ *   M_n = sum_{k<n} (Ct^>_k abar_k - Ct^<_k bbar_k),
+ * with abar_k = i rho_k P_k, bbar_k = -i (1 - rho_k) P_k and Ct^<_k, Ct^>_k
+ * the first three contractions of the chain on the functions of past time k
+ * (a_k = i P_k^dag rho_k, b_k = -i P_k^dag (1 - rho_k)).  Each step adds one
+ * past time to M and rotates v once: O(N^5) work per step instead of
+ * O(n N^5), with I equal to that of sb2_gkba_propagate up to rounding.
+ *   P        device, N x N complex, caller-owned state: P_{n0} on entry,
+ *            P_{n0+nsteps} on return (set to 1 by the call when n0 = 0);
+ *   M        device, N^4 complex, caller-owned state (row (p,r,n), column
+ *            l: M[((p N + r) N + n) N + l]); M_{n0} on entry (zeroed by the
+ *            call when n0 = 0), M_{n0+nsteps} on return;
+ *   rho_hist, I_hist, flags: as sb2_gkba_propagate (a resumed propagation
+ *            keeps the flags: past times join M only with
+ *            SB2_PROP_COLLISION set).  No U history is kept.
+ * Workspace: sb2_workspace_size(SB2_OP_PROPAGATE_LINEAR, N, any T, any prec)
+ * (independent of the history length).  Errors: as sb2_gkba_propagate (no
+ * prec argument); SB2_EINVAL for P or M == NULL.                          */
+int sb2_gkba_propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* P,
+                              void* M, void* I_hist, double dt, int flags, void* ws, size_t ws_bytes,
+                              void* stream);
 
 /* sb2_gkba_propagate_qp -- sb2_gkba_propagate with correlated (quasiparticle)
  * propagators in the GKBA, the extension the Conclusion names beside GW,

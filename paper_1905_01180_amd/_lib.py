@@ -20,7 +20,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "sb2.h")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16x3": 2, "bf16x6": 3}   # bf16x6: recognised, not built
 OPS = {"sigma": 0, "collision": 1, "collision_backward": 2, "rho_step": 3, "autotune": 4, "propagate": 5,
-       "collision_diagonal": 6, "collision_symmetric": 7, "propagate_diagonal": 8, "propagate_symmetric": 9}
+       "collision_diagonal": 6, "collision_symmetric": 7, "propagate_diagonal": 8, "propagate_symmetric": 9,
+       "propagate_linear": 10}
 VERTICES = {"diagonal": 1, "symmetric": 2}
 PROP_HF, PROP_COLLISION = 1, 2
 STATUS = {0: "SB2_OK", -1: "SB2_EINVAL", -2: "SB2_ESHAPE", -3: "SB2_EWORKSPACE", -4: "SB2_EHIP",
@@ -89,6 +90,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_collision_vertex.argtypes = [_i, _i, _i, _vp, _vp, _vp, _d, _vp, _vp, _vp, _sz, _vp]
         L.sb2_gkba_propagate_vertex.restype = _i
         L.sb2_gkba_propagate_vertex.argtypes = [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
+        L.sb2_gkba_propagate_linear.restype = _i
+        L.sb2_gkba_propagate_linear.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
         L.sb2_gkba_propagate_qp.restype = _i
         L.sb2_gkba_propagate_qp.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         L.sb2_gkba_propagate_switched.restype = _i
@@ -358,6 +361,31 @@ def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, 
     _call("sb2_gkba_propagate", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
           u_hist.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt), flags, p,
           ws.data_ptr(), ws.numel(), _stream(v.device))
+
+
+def sb2_gkba_propagate_linear(v, h, rho_hist, p_state, m_state, n0: int, nsteps: int, dt: float, hf: bool = True,
+                              collision: bool = True, i_hist=None):
+    """sb2_gkba_propagate with the sum over past times carried in the state
+    (p_state (N, N) = U(t_n, t_0), m_state (N^4,) the accumulated tensor),
+    float64; rho_hist (and i_hist) as for sb2_gkba_propagate, advanced in
+    place; at n0 = 0 the call initialises p_state and m_state."""
+    n = h.shape[0]
+    _check(v, "v", torch.float64, (n, n, n, n))
+    _check(h, "h", torch.complex128, (n, n))
+    _check(rho_hist, "rho_hist", torch.complex128, (rho_hist.shape[0], n, n))
+    _check(p_state, "p_state", torch.complex128, (n, n))
+    _check(m_state, "m_state", torch.complex128, (n ** 4,))
+    if rho_hist.shape[0] < n0 + nsteps + 1:
+        raise ValueError("rho_hist capacity too small for n0 + nsteps")
+    if i_hist is not None:
+        _check(i_hist, "i_hist", torch.complex128, (i_hist.shape[0], n, n))
+        if i_hist.shape[0] < n0 + nsteps:
+            raise ValueError("i_hist capacity too small for n0 + nsteps")
+    ws = workspace(sb2_workspace_size("propagate_linear", n, 1, 0), v.device)
+    flags = (PROP_HF if hf else 0) | (PROP_COLLISION if collision else 0)
+    _call("sb2_gkba_propagate_linear", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
+          p_state.data_ptr(), m_state.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt),
+          flags, ws.data_ptr(), ws.numel(), _stream(v.device))
 
 
 def sb2_gkba_propagate_vertex(vertex: str, param, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float,

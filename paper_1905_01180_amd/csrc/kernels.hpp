@@ -652,6 +652,20 @@ __global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
   if (e < n) x[e] = cmul(mk(a, b), x[e]);
 }
 
+// out <- the N x N identity
+__global__ void k_eye_c(int N, cplx* __restrict__ out) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (i64)N * N) out[e] = mk(e % (N + 1) == 0 ? 1.0 : 0.0, 0.0);
+}
+
+// out <- in^dag (N x N complex)
+__global__ void k_adjoint_c(int N, const cplx* __restrict__ in, cplx* __restrict__ out) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (i64)N * N) return;
+  const int i = (int)(e / N), j = (int)(e - (e / N) * N);
+  out[e] = conj_(in[(i64)j * N + i]);
+}
+
 // out <- a + b (complex)
 __global__ void k_add_c(i64 n, const cplx* __restrict__ a, const cplx* __restrict__ b, cplx* __restrict__ out) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;

@@ -794,6 +794,60 @@ BWD_DISPATCH(zg_m_k2)
     if (e_ != hipSuccess) return e_;          \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// Propagation with the collision integral accumulated over past times.  The
+// step propagators compose, U(t_n, t_k) = P_n P_k^dag with P_n = U(t_n, t_0),
+// so every GKBA function of past time k factors into P_n times a function of
+// t_k alone (or that function times P_n^dag): G^<(t_n, t_k) = P_n a_k with
+// a_k = i P_k^dag rho_k, G^>(t_n, t_k) = P_n b_k, G^<(t_k, t_n) = abar_k
+// P_n^dag with abar_k = i rho_k P_k, G^>(t_k, t_n) = bbar_k P_n^dag.  In the
+// self-energy (Eq. 13) the factors P_n attach to the t-side interaction
+// v_irpn only (its legs n, p and r), so with the rotated interaction
+//   vt(t_n)_{i r' p' n'} = sum_{n,p,r} v_irpn P_{n n'} P_{p p'} conj(P_{r r'})
+// the collision integral (Eq. 9) becomes
+//   I(t_n) = dt [ sum_{(n,p,r)} vt(t_n)[i][(n,p,r)] M_n[(n,p,r)][l] ] P_n^dag,
+//   M_n = sum_{k<n} ( Ct^>_k abar_k - Ct^<_k bbar_k ),
+// where Ct^<_k, Ct^>_k are the first three contractions of the chain (R1-R3)
+// on (a_k, a_k, bbar_k) and (b_k, b_k, abar_k): they do not depend on t_n.
+// One step therefore adds one past time to M and rotates v once, O(N^5)
+// work, instead of running the chain over all n past times.
+// ---------------------------------------------------------------------------
+struct LinPlan {
+  ChainPlan ch;                                   // chain buffers of one past time (two slices), float64
+  size_t c3;                                      // Ct of the two slices
+  size_t padj, x, y, gl, gg, glb, ggb;            // P_n^dag and the functions of the new past time
+  size_t heff, ustep, I, T1, ex1, ex2, ptmp, ip;  // per-step N x N scratch
+  size_t r1, r2;                                  // rotated interaction (N^4 complex each)
+  size_t part;                                    // split-K partials of the last contraction
+  int nz = 1, kchunk = 16;
+  size_t end;
+};
+
+LinPlan lin_plan(int N) {
+  LinPlan p;
+  const size_t n2 = (size_t)N * N, n3 = n2 * N, n4 = n3 * N;
+  const size_t m = al(n2 * C128);
+  p.ch = chain_plan(N, 1, SB2_FP64, 0, 1);
+  size_t o = p.ch.end;
+  p.c3 = o; o += al(2 * n4 * C128);
+  size_t* small[] = {&p.padj, &p.x, &p.y, &p.gl, &p.gg, &p.glb, &p.ggb, &p.heff, &p.ustep, &p.I, &p.T1,
+                     &p.ex1, &p.ex2, &p.ptmp, &p.ip};
+  for (size_t* q : small) { *q = o; o += m; }
+  p.r1 = o; o += al(n4 * C128);
+  p.r2 = o; o += al(n4 * C128);
+  // split-K of the K = N^3 contraction: about 2048 workgroups of N x N output tiles
+  const int bm = 16 * bwd_f(N);
+  const long long per_z = (long long)((N + bm - 1) / bm) * ((N + 63) / 64);
+  const long long nz = (2048 + per_z - 1) / per_z;
+  long long kc = ((long long)n3 + nz - 1) / nz;
+  kc = (kc + 15) / 16 * 16;
+  p.kchunk = (int)kc;
+  p.nz = (int)(((long long)n3 + kc - 1) / kc);
+  p.part = o; o += al((size_t)p.nz * n2 * C128);
+  p.end = o;
+  return p;
+}
+
 hipError_t collision_backward(int N, int T, const double* v, const void* h, const void* rho, double dt,
                               const void* gI, double* gv, void* gh, void* grho, const BwdPlan& b, void* ws,
                               hipStream_t s) {
@@ -1382,6 +1436,8 @@ size_t sb2_workspace_size(int op, int N, int T, int prec) {
     case SB2_OP_PROPAGATE_SYMMETRIC:
       if (T < 1 || T > SB2_MAX_T) return 0;
       return prop_plan(N, T, SB2_FP64, SB2_VERTEX_SYMMETRIC).end;
+    case SB2_OP_PROPAGATE_LINEAR:
+      return lin_plan(N).end;
     default:
       return 0;
   }
@@ -1854,6 +1910,153 @@ int propagate_general(int N, int n0, int nsteps, const double* v, const void* h,
                           reinterpret_cast<const cplx*>(sqp)));
   return SB2_OK;
 }
+
+// sb2_gkba_propagate_linear (see lin_plan for the factorisation).  P (N x N)
+// and M (N^4) are the caller's state; at n0 = 0 they start as 1 and 0.
+int propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* Pst,
+                     void* Mst, void* I_hist, double dt, int flags, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
+  if (!v || !h || !rho_hist || !Pst || !Mst || !ws || !finite_pos(dt)) return SB2_EINVAL;
+  if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
+  const LinPlan p = lin_plan(N);
+  if (ws_bytes < p.end) return SB2_EWORKSPACE;
+  SB2_ENTRY();
+  const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
+  SB2_CHECKS(ws, N, {2, v, n4}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, Pst, n0 > 0 ? n2 : 0},
+             {1, Mst, n0 > 0 ? n4 : 0});
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  auto P_ = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
+  cplx* rho = reinterpret_cast<cplx*>(rho_hist);
+  cplx* P = reinterpret_cast<cplx*>(Pst);
+  cplx* M = reinterpret_cast<cplx*>(Mst);
+  cplx *heff = P_(p.heff), *ustep = P_(p.ustep), *I = P_(p.I), *T1 = P_(p.T1), *ex1 = P_(p.ex1), *ex2 = P_(p.ex2);
+  cplx *padj = P_(p.padj), *X = P_(p.x), *Y = P_(p.y), *Gl = P_(p.gl), *Gg = P_(p.gg), *Glb = P_(p.glb),
+       *Ggb = P_(p.ggb), *ptmp = P_(p.ptmp), *ip = P_(p.ip), *r1 = P_(p.r1), *r2 = P_(p.r2), *C3 = P_(p.c3),
+       *part = P_(p.part);
+  const bool coll = (flags & SB2_PROP_COLLISION) != 0;
+  const size_t mb = (size_t)n2 * C128;
+  if (n0 == 0) {
+    hipLaunchKernelGGL(k_eye_c, dim3(blocks(n2, 256)), dim3(256), 0, s, N, P);
+    SB2_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks(4 * n4, 256)), dim3(256), 0, s, reinterpret_cast<unsigned*>(M),
+                       (int)(4 * n4), 0u);
+    SB2_TRY(hipGetLastError());
+  }
+  if (coll) SB2_TRY(prep_dispatch(SB2_FP64, N, v, p.ch, ws, s));
+  const ChainRefs refs = chain_refs(SB2_FP64, N, 2, p.ch, ws, C3);
+  const int n_end = n0 + nsteps;
+  for (int t = n0; t < n_end; ++t) {
+    cplx* rho_n = rho + (i64)t * n2;
+    // h_HF(t_n) and U_step (Eqs. 11, 12)
+    hipLaunchKernelGGL(k_sigma_hf, dim3(N), dim3(SIGMA_HF_THREADS), 0, s, N, v, rho_n,
+                       reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff, (const double*)nullptr,
+                       0);
+    SB2_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, heff, 0.0, -dt, ustep, ex1, ex2);
+    SB2_TRY(hipGetLastError());
+    if (coll && t > 0) {
+      StageTimer tm(7, s);
+      // rotated interaction, one leg per product:
+      //   r1[n'][i][r][p]  = sum_n P[n][n'] v[i][r][p][n]
+      //   r2[r'][n'][i][p] = sum_r conj(P[r][r']) r1[n'][i][r][p]
+      //   r1[p'][r'][n'][i] = sum_p P[p][p'] r2[r'][n'][i][p]   = vt_{i r' p' n'}
+      GemmArgs g = gdef();
+      g.M = N; g.N = (int)n3; g.K = N;
+      g.A = P; g.sAm = 1; g.sAk = N;
+      g.B = v; g.sBk = 1; g.sBn = N;
+      g.C = r1; g.sCm = n3; g.sCn = 1;
+      SB2_TRY(zg_m_cr(g, 1, s, N));
+      g = gdef();
+      g.M = N; g.N = N; g.K = N;
+      g.A = P; g.sAm = 1; g.sAk = N; g.conjA = 1;
+      g.B = r1; g.sBk = N; g.sBn = 1; g.sBbh = n2;
+      g.C = r2; g.sCm = n3; g.sCn = 1; g.sCbh = N;
+      SB2_TRY(zg_m(g, (int)n2, s, N));
+      g = gdef();
+      g.M = N; g.N = (int)n3; g.K = N;
+      g.A = P; g.sAm = 1; g.sAk = N;
+      g.B = r2; g.sBk = 1; g.sBn = N;
+      g.C = r1; g.sCm = n3; g.sCn = 1;
+      SB2_TRY(zg_m(g, 1, s, N));
+      // ip[i][l] = sum_{(p,r,n)} vt[i][(n,p,r)] M[(p,r,n)][l]   (split-K, float64 sum of the partials)
+      g = gdef();
+      g.M = N; g.N = N; g.K = (int)n3; g.kchunk = p.kchunk;
+      g.A = r1; g.sAm = 1; g.sAk = N;
+      g.B = M; g.sBk = N; g.sBn = 1;
+      g.C = part; g.sCm = N; g.sCn = 1; g.sCz = n2;
+      SB2_TRY(zg_m(g, 1, s, N));
+      hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n2, 256)), dim3(256), 0, s, n2, p.nz, part, ip, 0);
+      SB2_TRY(hipGetLastError());
+      // I = dt ip P^dag
+      g = gdef();
+      g.M = N; g.N = N; g.K = N;
+      g.A = ip; g.sAm = N; g.sAk = 1;
+      g.B = P; g.sBk = 1; g.sBn = N; g.conjB = 1;
+      g.C = I; g.sCm = N; g.sCn = 1; g.alpha_re = dt;
+      SB2_TRY(zgemm(g, 1, s));
+    } else {
+      hipLaunchKernelGGL(k_fill_u32, dim3(blocks(4 * n2, 256)), dim3(256), 0, s, reinterpret_cast<unsigned*>(I),
+                         (int)(4 * n2), 0u);
+      SB2_TRY(hipGetLastError());
+    }
+    if (I_hist) SB2_TRY(hipMemcpyAsync(reinterpret_cast<cplx*>(I_hist) + (i64)t * n2, I, mb,
+                                       hipMemcpyDeviceToDevice, s));
+    // rho_{n+1} = U_step rho_n U_step^dag - dt (I + I^dag) (Eq. 8)
+    GemmArgs g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = ustep; g.sAm = N; g.sAk = 1;
+    g.B = rho_n; g.sBk = N; g.sBn = 1;
+    g.C = T1; g.sCm = N; g.sCn = 1;
+    SB2_TRY(zgemm(g, 1, s));
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = T1; g.sAm = N; g.sAk = 1;
+    g.B = ustep; g.sBk = 1; g.sBn = N; g.conjB = 1;
+    g.C = ex1; g.sCm = N; g.sCn = 1;
+    SB2_TRY(zgemm(g, 1, s));
+    hipLaunchKernelGGL(k_rho_finish, dim3(blocks(n2, 256)), dim3(256), 0, s, N, ex1, I, dt, rho_n + n2);
+    SB2_TRY(hipGetLastError());
+    if (coll) {
+      StageTimer tm(7, s);
+      // past time t joins M: functions a, b, abar, bbar from P_t (the GKBA set-up with U = P_t^dag)
+      hipLaunchKernelGGL(k_adjoint_c, dim3(blocks(n2, 256)), dim3(256), 0, s, N, P, padj);
+      SB2_TRY(hipGetLastError());
+      g = gdef();
+      g.M = N; g.N = N; g.K = N;
+      g.A = padj; g.sAm = N; g.sAk = 1;
+      g.B = rho_n; g.sBk = N; g.sBn = 1;
+      g.C = X; g.sCm = N; g.sCn = 1;
+      SB2_TRY(zgemm(g, 1, s));
+      g.A = rho_n; g.B = P; g.C = Y;
+      SB2_TRY(zgemm(g, 1, s));
+      hipLaunchKernelGGL(k_gkba, dim3(blocks(n2, 256)), dim3(256), 0, s, N, 1, padj, X, Y, Gl, Gg, Glb, Ggb);
+      SB2_TRY(hipGetLastError());
+      SB2_TRY(pack_dispatch(SB2_FP64, N, 1, Gl, Gg, Glb, Ggb, 0, p.ch, ws, s));
+      SB2_TRY((launch_stage<PK_F64, 0>(refs, s)));
+      SB2_TRY((launch_stage<PK_F64, 1>(refs, s)));
+      SB2_TRY((launch_stage<PK_F64, 2>(refs, s)));
+      // M[(p,r,n)][l] += Ct^>[j][(n,p,r)] abar[j][l] - Ct^<[j][(n,p,r)] bbar[j][l]
+      for (int sig = 0; sig < 2; ++sig) {
+        g = gdef();
+        g.M = (int)n3; g.N = N; g.K = N;
+        g.A = C3 + (i64)sig * n4; g.sAm = 1; g.sAk = n3;
+        g.B = sig ? Glb : Ggb; g.sBk = N; g.sBn = 1;
+        g.C = M; g.Mlo = (int)n2; g.sCmh = N; g.sCm = n2; g.sCn = 1;
+        g.alpha_re = sig ? 1.0 : -1.0; g.beta1 = 1;
+        SB2_TRY(zg_n(g, 1, s, N));
+      }
+    }
+    // P_{n+1} = U_step P_n
+    g = gdef();
+    g.M = N; g.N = N; g.K = N;
+    g.A = ustep; g.sAm = N; g.sAk = 1;
+    g.B = P; g.sBk = N; g.sBn = 1;
+    g.C = ptmp; g.sCm = N; g.sCn = 1;
+    SB2_TRY(zgemm(g, 1, s));
+    SB2_TRY(hipMemcpyAsync(P, ptmp, mb, hipMemcpyDeviceToDevice, s));
+  }
+  return SB2_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1870,6 +2073,12 @@ int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, cons
   if (!lambda) return SB2_EINVAL;
   return propagate_general(N, n0, nsteps, v, h, rho_hist, U_hist, I_hist, lambda, dt, flags, prec, ws, ws_bytes,
                            stream);
+}
+
+int sb2_gkba_propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* P,
+                              void* M, void* I_hist, double dt, int flags, void* ws, size_t ws_bytes,
+                              void* stream) {
+  return propagate_linear(N, n0, nsteps, v, h, rho_hist, P, M, I_hist, dt, flags, ws, ws_bytes, stream);
 }
 
 int sb2_gkba_propagate_qp(int N, int n0, int nsteps, const double* v, const void* h, const void* sigma_qp,

@@ -161,3 +161,19 @@ def test_qp_propagation_arguments(L):
     assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, 3, FAKE, BIG, None) == -5   # split BF16
     assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 8, 0, FAKE, BIG, None) == -1   # unknown flag
     assert p(8, 0, 4, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, 0, FAKE, 64, None) == -3
+
+
+def test_linear_propagation_arguments(L):
+    p = L.sb2_gkba_propagate_linear
+    # argument order: N, n0, nsteps, v, h, rho, P, M, I, dt, flags, ws, ws_bytes, stream
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, None, FAKE, None, 0.05, 3, FAKE, BIG, None) == -1    # no P
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 3, FAKE, BIG, None) == -1    # no M
+    assert p(0, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, -1, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, float("nan"), 3, FAKE, BIG, None) == -1
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 4, FAKE, BIG, None) == -1   # unknown flag
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, 64, None) == -3
+    ws = _lib.sb2_workspace_size
+    # independent of the history length, and far below the growing-history propagation at long T
+    assert ws("propagate_linear", 16, 1) == ws("propagate_linear", 16, 60000) > 0
+    assert ws("propagate_linear", 16, 1) < ws("propagate", 16, 60000, "fp64")

@@ -1,0 +1,94 @@
+"""Propagation with the sum over past times carried along
+(sb2_gkba_propagate_linear) against the propagation oracle
+(oracle/gkba_driver.propagate, which sums every past time at every step):
+generic and real-orbital interactions, with and without the HF self-energy,
+at ragged sizes; against the device's own growing-history propagation
+(sb2_gkba_propagate) at N = 20 and 40; a resumed run equal to one call bit for
+bit; and no collisions when they are switched off.  Bar: float64, 1e-11
+relative (Frobenius) on every rho and I."""
+import numpy as np
+import pytest
+
+from oracle import gkba_driver as d
+from paper_1905_01180_amd import inputs as gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+DT = 0.05
+
+
+def relf(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _system(n, seed, kind="generic"):
+    g = gen.rng(77, seed, 0)
+    h = gen.hermitian_gaussian(n, g)
+    v = gen.interaction_generic(n, g) if kind == "generic" else gen.interaction_real_orbitals(n, g)
+    return h, v, gen.density_matrix(n, g)
+
+
+def run_linear(v, h, rho0, steps, hf=True, coll=True, split=None):
+    from paper_1905_01180_amd import _lib
+    n = h.shape[0]
+    rho = torch.zeros((steps + 1, n, n), dtype=torch.complex128, device=DEV)
+    ih = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    p = torch.zeros((n, n), dtype=torch.complex128, device=DEV)
+    m = torch.zeros((n ** 4,), dtype=torch.complex128, device=DEV)
+    rho[0].copy_(_dev(rho0))
+    vd, hd = _dev(v), _dev(h)
+    for a, b in ([(0, steps)] if split is None else [(0, split), (split, steps)]):
+        _lib.sb2_gkba_propagate_linear(vd, hd, rho, p, m, a, b - a, DT, hf=hf, collision=coll, i_hist=ih)
+    return rho.cpu().numpy(), ih.cpu().numpy(), p.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,kind,hf", [(4, "generic", True), (9, "generic", False), (17, "orbitals", True)])
+def test_linear_matches_oracle(n, kind, hf):
+    steps = 10
+    h, v, rho0 = _system(n, n, kind)
+    print(f"case: linear N={n} {kind} hf={hf}", flush=True)
+    rho, ih, p = run_linear(v, h, rho0, steps, hf=hf)
+    ref = d.propagate(v, h, DT, steps, d.new_state(rho0), hf=hf)
+    e_rho = max(relf(rho[m], ref["rho"][m]) for m in range(steps + 1))
+    e_i = max(relf(ih[m], ref["i"][m]) for m in range(1, steps))
+    print(f"linear N={n}: rho {e_rho:.2e}, I {e_i:.2e}", flush=True)
+    assert e_rho < 1e-11 and e_i < 1e-11
+    assert np.abs(ih[0]).max() == 0.0
+    # the carried propagator is U(t_steps, t_0) = the oldest entry of the oracle's history
+    assert relf(p, ref["u"][0]) < 1e-12
+
+
+@pytest.mark.parametrize("n,steps", [(20, 24), (40, 12)])
+def test_linear_matches_growing_history_propagation(n, steps):
+    from paper_1905_01180_amd import _lib
+    h, v, rho0 = _system(n, 100 + n, "orbitals")
+    print(f"case: linear vs growing history N={n} steps={steps}", flush=True)
+    rho_l, ih_l, _ = run_linear(v, h, rho0, steps)
+    rho = torch.zeros((steps + 1, n, n), dtype=torch.complex128, device=DEV)
+    u = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    ih = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    rho[0].copy_(_dev(rho0))
+    _lib.sb2_gkba_propagate(_dev(v), _dev(h), rho, u, 0, steps, DT, "fp64", i_hist=ih)
+    rho, ih = rho.cpu().numpy(), ih.cpu().numpy()
+    e_rho = max(relf(rho_l[m], rho[m]) for m in range(steps + 1))
+    e_i = max(relf(ih_l[m], ih[m]) for m in range(1, steps))
+    print(f"linear vs growing N={n}: rho {e_rho:.2e}, I {e_i:.2e}", flush=True)
+    assert e_rho < 1e-11 and e_i < 1e-11
+
+
+def test_linear_resume_and_no_collision():
+    n, steps = 11, 9
+    h, v, rho0 = _system(n, 5)
+    print("case: linear resume / no collision N=11", flush=True)
+    one = run_linear(v, h, rho0, steps)
+    two = run_linear(v, h, rho0, steps, split=4)
+    assert all(np.array_equal(a, b) for a, b in zip(one, two))
+    rho, ih, _ = run_linear(v, h, rho0, steps, coll=False)
+    assert np.abs(ih).max() == 0.0
+    ref = d.propagate(v, h, DT, steps, d.new_state(rho0), collision=False)
+    assert max(relf(rho[m], ref["rho"][m]) for m in range(steps + 1)) < 1e-12
