@@ -291,15 +291,19 @@ int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, cons
  *   M        device, N^4 complex, caller-owned state (row (p,r,n), column
  *            l: M[((p N + r) N + n) N + l]); M_{n0} on entry (zeroed by the
  *            call when n0 = 0), M_{n0+nsteps} on return;
+ *   lambda   optional (NULL: constant coupling 1) device array of n0 + nsteps
+ *            float64 values lambda(t_m), the interaction being lambda(t) v as
+ *            in sb2_gkba_propagate_switched: past time k joins M weighted by
+ *            lambda(t_k), I(t_n) and Sigma_HF(t_n) carry lambda(t_n);
  *   rho_hist, I_hist, flags: as sb2_gkba_propagate (a resumed propagation
- *            keeps the flags: past times join M only with
- *            SB2_PROP_COLLISION set).  No U history is kept.
+ *            keeps the flags and the coupling history: past times join M
+ *            only with SB2_PROP_COLLISION set).  No U history is kept.
  * Workspace: sb2_workspace_size(SB2_OP_PROPAGATE_LINEAR, N, any T, any prec)
  * (independent of the history length).  Errors: as sb2_gkba_propagate (no
  * prec argument); SB2_EINVAL for P or M == NULL.                          */
 int sb2_gkba_propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* P,
-                              void* M, void* I_hist, double dt, int flags, void* ws, size_t ws_bytes,
-                              void* stream);
+                              void* M, void* I_hist, const double* lambda, double dt, int flags, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* sb2_gkba_propagate_qp -- sb2_gkba_propagate with correlated (quasiparticle)
  * propagators in the GKBA, the extension the Conclusion names beside GW,

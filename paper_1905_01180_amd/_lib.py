@@ -91,7 +91,8 @@ def lib() -> ctypes.CDLL:
         L.sb2_gkba_propagate_vertex.restype = _i
         L.sb2_gkba_propagate_vertex.argtypes = [_i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
         L.sb2_gkba_propagate_linear.restype = _i
-        L.sb2_gkba_propagate_linear.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz, _vp]
+        L.sb2_gkba_propagate_linear.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _sz,
+                                                 _vp]
         L.sb2_gkba_propagate_qp.restype = _i
         L.sb2_gkba_propagate_qp.argtypes = [_i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i, _i, _vp, _sz, _vp]
         L.sb2_gkba_propagate_switched.restype = _i
@@ -364,11 +365,12 @@ def sb2_gkba_propagate(v, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float, 
 
 
 def sb2_gkba_propagate_linear(v, h, rho_hist, p_state, m_state, n0: int, nsteps: int, dt: float, hf: bool = True,
-                              collision: bool = True, i_hist=None):
+                              collision: bool = True, i_hist=None, switch=None):
     """sb2_gkba_propagate with the sum over past times carried in the state
     (p_state (N, N) = U(t_n, t_0), m_state (N^4,) the accumulated tensor),
     float64; rho_hist (and i_hist) as for sb2_gkba_propagate, advanced in
-    place; at n0 = 0 the call initialises p_state and m_state."""
+    place; at n0 = 0 the call initialises p_state and m_state.  switch:
+    optional device float64 coupling history lambda(t_m), m < n0 + nsteps."""
     n = h.shape[0]
     _check(v, "v", torch.float64, (n, n, n, n))
     _check(h, "h", torch.complex128, (n, n))
@@ -381,11 +383,16 @@ def sb2_gkba_propagate_linear(v, h, rho_hist, p_state, m_state, n0: int, nsteps:
         _check(i_hist, "i_hist", torch.complex128, (i_hist.shape[0], n, n))
         if i_hist.shape[0] < n0 + nsteps:
             raise ValueError("i_hist capacity too small for n0 + nsteps")
+    if switch is not None:
+        _check(switch, "switch", torch.float64, (switch.shape[0],))
+        if switch.shape[0] < n0 + nsteps:
+            raise ValueError("switch must hold lambda(t_m) for every m < n0 + nsteps")
     ws = workspace(sb2_workspace_size("propagate_linear", n, 1, 0), v.device)
     flags = (PROP_HF if hf else 0) | (PROP_COLLISION if collision else 0)
     _call("sb2_gkba_propagate_linear", n, int(n0), int(nsteps), v.data_ptr(), h.data_ptr(), rho_hist.data_ptr(),
-          p_state.data_ptr(), m_state.data_ptr(), i_hist.data_ptr() if i_hist is not None else None, float(dt),
-          flags, ws.data_ptr(), ws.numel(), _stream(v.device))
+          p_state.data_ptr(), m_state.data_ptr(), i_hist.data_ptr() if i_hist is not None else None,
+          switch.data_ptr() if switch is not None else None, float(dt), flags, ws.data_ptr(), ws.numel(),
+          _stream(v.device))
 
 
 def sb2_gkba_propagate_vertex(vertex: str, param, h, rho_hist, u_hist, n0: int, nsteps: int, dt: float,

@@ -652,6 +652,12 @@ __global__ void k_scale_c(i64 n, cplx* __restrict__ x, double a, double b) {
   if (e < n) x[e] = cmul(mk(a, b), x[e]);
 }
 
+// x <- lam[idx] x for n complex values (a coupling weight read on the device)
+__global__ void k_scale_by(i64 n, cplx* __restrict__ x, const double* __restrict__ lam, int idx) {
+  const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = x[e] * lam[idx];
+}
+
 // out <- the N x N identity
 __global__ void k_eye_c(int N, cplx* __restrict__ out) {
   const i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x;

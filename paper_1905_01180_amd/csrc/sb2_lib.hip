@@ -1913,8 +1913,11 @@ int propagate_general(int N, int n0, int nsteps, const double* v, const void* h,
 
 // sb2_gkba_propagate_linear (see lin_plan for the factorisation).  P (N x N)
 // and M (N^4) are the caller's state; at n0 = 0 they start as 1 and 0.
+// lam (optional): coupling history; past time k joins M weighted by
+// lambda(t_k), I(t_n) and Sigma_HF(t_n) carry lambda(t_n).
 int propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* Pst,
-                     void* Mst, void* I_hist, double dt, int flags, void* ws, size_t ws_bytes, void* stream) {
+                     void* Mst, void* I_hist, const double* lam, double dt, int flags, void* ws, size_t ws_bytes,
+                     void* stream) {
   if (N < 1 || N > SB2_MAX_N || n0 < 0 || nsteps < 1 || (long long)n0 + nsteps > SB2_MAX_T) return SB2_ESHAPE;
   if (!v || !h || !rho_hist || !Pst || !Mst || !ws || !finite_pos(dt)) return SB2_EINVAL;
   if (flags & ~(SB2_PROP_HF | SB2_PROP_COLLISION)) return SB2_EINVAL;
@@ -1923,7 +1926,7 @@ int propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, 
   SB2_ENTRY();
   const i64 n = N, n2 = n * n, n3 = n2 * n, n4 = n3 * n;
   SB2_CHECKS(ws, N, {2, v, n4}, {0, h, 1}, {0, rho_hist, n0 + 1}, {1, Pst, n0 > 0 ? n2 : 0},
-             {1, Mst, n0 > 0 ? n4 : 0});
+             {1, Mst, n0 > 0 ? n4 : 0}, {2, lam, lam ? (i64)n0 + nsteps : 0});
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   auto P_ = [&](size_t off) { return reinterpret_cast<cplx*>(at(ws, off)); };
   cplx* rho = reinterpret_cast<cplx*>(rho_hist);
@@ -1949,8 +1952,7 @@ int propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, 
     cplx* rho_n = rho + (i64)t * n2;
     // h_HF(t_n) and U_step (Eqs. 11, 12)
     hipLaunchKernelGGL(k_sigma_hf, dim3(N), dim3(SIGMA_HF_THREADS), 0, s, N, v, rho_n,
-                       reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff, (const double*)nullptr,
-                       0);
+                       reinterpret_cast<const cplx*>(h), (flags & SB2_PROP_HF) ? 1 : 0, heff, lam, t);
     SB2_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_expm, dim3(1), dim3(EXPM_THREADS), 0, s, N, heff, 0.0, -dt, ustep, ex1, ex2);
     SB2_TRY(hipGetLastError());
@@ -1994,6 +1996,10 @@ int propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, 
       g.B = P; g.sBk = 1; g.sBn = N; g.conjB = 1;
       g.C = I; g.sCm = N; g.sCn = 1; g.alpha_re = dt;
       SB2_TRY(zgemm(g, 1, s));
+      if (lam) {
+        hipLaunchKernelGGL(k_scale_by, dim3(blocks(n2, 256)), dim3(256), 0, s, n2, I, lam, t);
+        SB2_TRY(hipGetLastError());
+      }
     } else {
       hipLaunchKernelGGL(k_fill_u32, dim3(blocks(4 * n2, 256)), dim3(256), 0, s, reinterpret_cast<unsigned*>(I),
                          (int)(4 * n2), 0u);
@@ -2035,7 +2041,14 @@ int propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, 
       SB2_TRY((launch_stage<PK_F64, 0>(refs, s)));
       SB2_TRY((launch_stage<PK_F64, 1>(refs, s)));
       SB2_TRY((launch_stage<PK_F64, 2>(refs, s)));
-      // M[(p,r,n)][l] += Ct^>[j][(n,p,r)] abar[j][l] - Ct^<[j][(n,p,r)] bbar[j][l]
+      // M[(p,r,n)][l] += lambda(t_t) (Ct^>[j][(n,p,r)] abar[j][l] - Ct^<[j][(n,p,r)] bbar[j][l])
+      // (the packed chain operands are already taken, so abar and bbar carry the weight)
+      if (lam) {
+        hipLaunchKernelGGL(k_scale_by, dim3(blocks(n2, 256)), dim3(256), 0, s, n2, Glb, lam, t);
+        SB2_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_scale_by, dim3(blocks(n2, 256)), dim3(256), 0, s, n2, Ggb, lam, t);
+        SB2_TRY(hipGetLastError());
+      }
       for (int sig = 0; sig < 2; ++sig) {
         g = gdef();
         g.M = (int)n3; g.N = N; g.K = N;
@@ -2076,9 +2089,9 @@ int sb2_gkba_propagate_switched(int N, int n0, int nsteps, const double* v, cons
 }
 
 int sb2_gkba_propagate_linear(int N, int n0, int nsteps, const double* v, const void* h, void* rho_hist, void* P,
-                              void* M, void* I_hist, double dt, int flags, void* ws, size_t ws_bytes,
-                              void* stream) {
-  return propagate_linear(N, n0, nsteps, v, h, rho_hist, P, M, I_hist, dt, flags, ws, ws_bytes, stream);
+                              void* M, void* I_hist, const double* lambda, double dt, int flags, void* ws,
+                              size_t ws_bytes, void* stream) {
+  return propagate_linear(N, n0, nsteps, v, h, rho_hist, P, M, I_hist, lambda, dt, flags, ws, ws_bytes, stream);
 }
 
 int sb2_gkba_propagate_qp(int N, int n0, int nsteps, const double* v, const void* h, const void* sigma_qp,

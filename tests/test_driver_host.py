@@ -165,14 +165,14 @@ def test_qp_propagation_arguments(L):
 
 def test_linear_propagation_arguments(L):
     p = L.sb2_gkba_propagate_linear
-    # argument order: N, n0, nsteps, v, h, rho, P, M, I, dt, flags, ws, ws_bytes, stream
-    assert p(8, 0, 2, FAKE, FAKE, FAKE, None, FAKE, None, 0.05, 3, FAKE, BIG, None) == -1    # no P
-    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 3, FAKE, BIG, None) == -1    # no M
-    assert p(0, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
-    assert p(8, -1, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, BIG, None) == -2
-    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, float("nan"), 3, FAKE, BIG, None) == -1
-    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 4, FAKE, BIG, None) == -1   # unknown flag
-    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, 0.05, 3, FAKE, 64, None) == -3
+    # argument order: N, n0, nsteps, v, h, rho, P, M, I, lambda, dt, flags, ws, ws_bytes, stream
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, None, FAKE, None, None, 0.05, 3, FAKE, BIG, None) == -1    # no P
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, None, None, None, 0.05, 3, FAKE, BIG, None) == -1    # no M
+    assert p(0, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, -1, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 3, FAKE, BIG, None) == -2
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, float("nan"), 3, FAKE, BIG, None) == -1
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 4, FAKE, BIG, None) == -1   # unknown flag
+    assert p(8, 0, 2, FAKE, FAKE, FAKE, FAKE, FAKE, None, None, 0.05, 3, FAKE, 64, None) == -3
     ws = _lib.sb2_workspace_size
     # independent of the history length, and far below the growing-history propagation at long T
     assert ws("propagate_linear", 16, 1) == ws("propagate_linear", 16, 60000) > 0

@@ -92,3 +92,36 @@ def test_linear_resume_and_no_collision():
     assert np.abs(ih).max() == 0.0
     ref = d.propagate(v, h, DT, steps, d.new_state(rho0), collision=False)
     assert max(relf(rho[m], ref["rho"][m]) for m in range(steps + 1)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 13])
+def test_linear_switched_matches_oracle(n):
+    # adiabatic switching with the carried sum: past time k weighted by
+    # lambda(t_k), I(t_n) and Sigma_HF(t_n) by lambda(t_n)
+    from paper_1905_01180_amd import _lib
+    steps = 12
+    h, v, rho0 = _system(n, 40 + n)
+    t = DT * np.arange(steps)
+    lam = np.sin(0.5 * np.pi * np.minimum(t / 0.4, 1.0)) ** 2 * (1.0 + 0.5 * np.sin(2 * np.pi * t / 0.3))
+    print(f"case: linear switched N={n}", flush=True)
+    rho = torch.zeros((steps + 1, n, n), dtype=torch.complex128, device=DEV)
+    ih = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    p = torch.zeros((n, n), dtype=torch.complex128, device=DEV)
+    m = torch.zeros((n ** 4,), dtype=torch.complex128, device=DEV)
+    rho[0].copy_(_dev(rho0))
+    _lib.sb2_gkba_propagate_linear(_dev(v), _dev(h), rho, p, m, 0, steps, DT, i_hist=ih, switch=_dev(lam))
+    rho, ih = rho.cpu().numpy(), ih.cpu().numpy()
+    ref = d.propagate(v, h, DT, steps, d.new_state(rho0), switch=lam)
+    e_rho = max(relf(rho[k], ref["rho"][k]) for k in range(steps + 1))
+    e_i = max(relf(ih[k], ref["i"][k]) for k in range(2, steps))
+    print(f"linear switched N={n}: rho {e_rho:.2e}, I {e_i:.2e}", flush=True)
+    assert e_rho < 1e-11 and e_i < 1e-11
+    # lambda = 1 reproduces the unswitched run bit for bit
+    one = run_linear(v, h, rho0, steps)
+    rho1 = torch.zeros((steps + 1, n, n), dtype=torch.complex128, device=DEV)
+    ih1 = torch.zeros((steps, n, n), dtype=torch.complex128, device=DEV)
+    p.zero_()
+    rho1[0].copy_(_dev(rho0))
+    _lib.sb2_gkba_propagate_linear(_dev(v), _dev(h), rho1, p, m, 0, steps, DT, i_hist=ih1,
+                                   switch=_dev(np.ones(steps)))
+    assert np.array_equal(rho1.cpu().numpy(), one[0]) and np.array_equal(ih1.cpu().numpy(), one[1])
