@@ -119,8 +119,9 @@ def eq4_error(torch, _lib, dev, prec, n, t, nk=3):
 def legs(torch, _lib, gen, dev, prec):
     """Short measurements of the other workloads, reported beside the headline:
     config 1 (N=50, T=500, float64) against its stored oracle values, config 3
-    (N=64, T=256: forward and hand-written adjoint, float64) and config 4 (32
-    systems, N 24..96, T 64..512: one batched call against 32 single calls)."""
+    (N=64, T=256: forward and hand-written adjoint, float64), config 4 (32
+    systems, N 24..96, T 64..512: one batched call against 32 single calls)
+    and the propagation with the carried sum over past times at N = 100."""
     out = {}
 
     def tsec(fn, reps):
@@ -168,6 +169,24 @@ def legs(torch, _lib, gen, dev, prec):
     out["c4_batched"] = {"workload": "32 systems, N ~ U{24..96}, T ~ U{64..512}, " + prec,
                          "batched_s": t_grp, "sequential_s": t_seq, "speedup": t_seq / t_grp,
                          "tflops_algorithmic": flops / t_grp / 1e12}
+    del data
+    # propagation with the sum over past times carried (float64): steps 2..6 from t_0
+    s = gen.make_system(100, 1, config_id=2)
+    v, h = torch.from_numpy(s.v).to(dev), torch.from_numpy(s.h).to(dev)
+    rho = torch.zeros((8, 100, 100), dtype=torch.complex128, device=dev)
+    rho[0].copy_(torch.from_numpy(s.rho_hist[0]))
+    pst = torch.zeros((100, 100), dtype=torch.complex128, device=dev)
+    mst = torch.zeros((100 ** 4,), dtype=torch.complex128, device=dev)
+    _lib.sb2_gkba_propagate_linear(v, h, rho, pst, mst, 0, 2, s.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _lib.sb2_gkba_propagate_linear(v, h, rho, pst, mst, 2, 5, s.dt)
+    torch.cuda.synchronize()
+    t_lin = (time.perf_counter() - t0) / 5
+    out["propagate_linear_fp64"] = {
+        "workload": "GKBA propagation N=100, float64, sum over past times carried (cost per step independent "
+                    "of the history)", "ms_per_step": 1e3 * t_lin,
+        "tflops_algorithmic": 84.0 * 1e10 / t_lin / 1e12}
     return out
 
 
@@ -366,7 +385,7 @@ def main():
 
     other = None
     if not args.no_legs and (args.n, args.t) == (100, 1000):
-        log("other workloads: N=50 FP64, adjoint N=64 T=256, 32-system batch")
+        log("other workloads: N=50 FP64, adjoint N=64 T=256, 32-system batch, carried-sum propagation N=100")
         other = legs(torch, _lib, gen, dev, args.prec)
 
     cpu = None
