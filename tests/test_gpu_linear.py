@@ -3,7 +3,7 @@
 (oracle/gkba_driver.propagate, which sums every past time at every step):
 generic and real-orbital interactions, with and without the HF self-energy,
 at ragged sizes; against the device's own growing-history propagation
-(sb2_gkba_propagate) at N = 20 and 40; a resumed run equal to one call bit for
+(sb2_gkba_propagate) at N = 20, 40 and the limit 128; a resumed run equal to one call bit for
 bit; and no collisions when they are switched off.  Bar: float64, 1e-11
 relative (Frobenius) on every rho and I."""
 import numpy as np
@@ -63,7 +63,7 @@ def test_linear_matches_oracle(n, kind, hf):
     assert relf(p, ref["u"][0]) < 1e-12
 
 
-@pytest.mark.parametrize("n,steps", [(20, 24), (40, 12)])
+@pytest.mark.parametrize("n,steps", [(20, 24), (40, 12), (128, 4)])
 def test_linear_matches_growing_history_propagation(n, steps):
     from paper_1905_01180_amd import _lib
     h, v, rho0 = _system(n, 100 + n, "orbitals")
