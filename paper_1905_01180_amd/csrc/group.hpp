@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(64 * (NT + 1)) k_r23_group(const ChainRefs* __
 }
 
 template <int FS>
-__global__ void __launch_bounds__(512) k_r4_group(const ChainRefs* __restrict__ refs, const SubGroup t) {
+__global__ void __launch_bounds__(R4_THREADS) k_r4_group(const ChainRefs* __restrict__ refs, const SubGroup t) {
   const long long b = blockIdx.x;
   const int i = sub_member(t, b);
   const R4Args a = r4_args(refs[t.idx[i]]);

@@ -528,10 +528,9 @@ template <int FS>
 hipError_t launch_r4_fs(const ChainRefs& r, hipStream_t st) {
   const R4Args a = r4_args(r);
   StageTimer tm(3, st);
-  if ((a.kc & 1) == 0)
-    hipLaunchKernelGGL((k_r4_h16<FS, true>), dim3((unsigned)r4_tiles(a), (unsigned)r.N), dim3(512), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_r4_h16<FS, false>), dim3((unsigned)r4_tiles(a), (unsigned)r.N), dim3(512), 0, st, a);
+  const dim3 grid((unsigned)r4_tiles(a), (unsigned)r.N);
+  if ((a.kc & 1) == 0) hipLaunchKernelGGL((k_r4_h16<FS, true>), grid, dim3(R4_THREADS), 0, st, a);
+  else hipLaunchKernelGGL((k_r4_h16<FS, false>), grid, dim3(R4_THREADS), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1188,7 +1187,7 @@ hipError_t launch_bucket(const ChainRefs* d, const SubGroup& t23, const SubGroup
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   StageTimer tm(3, st);
-  hipLaunchKernelGGL((k_r4_group<NT>), dim3((unsigned)t4.off[t4.count]), dim3(512), 0, st, d, t4);
+  hipLaunchKernelGGL((k_r4_group<NT>), dim3((unsigned)t4.off[t4.count]), dim3(R4_THREADS), 0, st, d, t4);
   return hipGetLastError();
 }
 
