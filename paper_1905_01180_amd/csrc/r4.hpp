@@ -57,8 +57,8 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
   constexpr int NCOL = 64, KS = 64, NKG = KS / 32;
   constexpr int FSP = (FS + 1) / 2 * 2, FH = FSP / 2;
   constexpr int LP = KS + 16;                           // 160-byte rows: 16 u bytes, u = 2 mod 4 (conflict-free fragment reads)
-  static_assert((2 * 16 * FSP * (KS / 8)) % NPT == 0, "whole V' items per producer thread");
-  constexpr int PV = 2 * 16 * FSP * (KS / 8) / NPT;     // V' items (hx8) per producer thread
+  static_assert((2 * 16 * FS * (KS / 8)) % NPT == 0, "whole V' items per producer thread");
+  constexpr int PV = 2 * 16 * FS * (KS / 8) / NPT;      // V' items (hx8) per producer thread (= FS)
   constexpr int PC = NCOL * KS / 2 / NPT;                // C loads (2 complex each) per producer thread
   __shared__ __attribute__((aligned(16))) _Float16 sV[2][2][16 * FSP][LP];
   __shared__ __attribute__((aligned(16))) _Float16 sC[2][4][NCOL][LP];
@@ -77,31 +77,31 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
     const float* Xz = a.X + 2 * ((i64)by * a.xchunk);
     const float sx = split_scale(a.xmax);
     // V' item u: 8-wide k group vh of combined (plane, row) R0 + (NPT / 8) u
+    // over the 16 FS rows of each plane that are multiplied (the rows of the
+    // padding fragment are never read)
     const int vh = 8 * (pt & 7), R0 = pt >> 3;
     auto vrow = [&](int u, int& pl, int& r) {
       const int R = R0 + (NPT / 8) * u;
-      pl = R >= 16 * FSP ? 1 : 0;
-      r = R - pl * 16 * FSP;
+      pl = R >= 16 * FS ? 1 : 0;
+      r = R - pl * 16 * FS;
     };
-    // Loads only clamp their addresses, as in the plain kernel: rows past M,
-    // k past the chunk and slabs past the end read in-bounds data whose
-    // products vanish or are never used.  Each load is a uniform base plus a
-    // 32-bit byte offset (the plane of item u is the same in every lane, as
-    // 16 FSP is a multiple of NPT / 8).
+    // Loads only clamp their addresses: rows past M read row M - 1 (their
+    // products land in output rows that are never written), k past the chunk
+    // reads its last 8-group (the chunk padding is zero), slabs past the end
+    // are never multiplied.  Each load is the chunk's base plus a 32-bit byte
+    // offset (both planes of V' span under 1.1e9 bytes for N <= 128).
     unsigned vro[PV];
 #pragma unroll
     for (int u = 0; u < PV; ++u) {
       int pl, r;
       vrow(u, pl, r);
-      vro[u] = 2u * (unsigned)((i64)min(r, a.M - 1) * a.ldv);
+      vro[u] = 2u * (unsigned)(pl * a.vplane + (i64)min(r, a.M - 1) * a.ldv);
     }
     auto load_v = [&](int s, hx8 (&dst)[PV]) {
       const unsigned ko = 2u * (unsigned)min(s * KS + vh, (int)a.vchunk - 8);
+      const char* base = reinterpret_cast<const char*>(Vz);
 #pragma unroll
-      for (int u = 0; u < PV; ++u) {
-        const char* base = reinterpret_cast<const char*>(Vz + (NPT / 8 * u >= 16 * FSP ? a.vplane : 0));
-        dst[u] = *reinterpret_cast<const hx8*>(base + (vro[u] + ko));
-      }
+      for (int u = 0; u < PV; ++u) dst[u] = *reinterpret_cast<const hx8*>(base + (vro[u] + ko));
     };
     auto store_v = [&](int buf, const hx8 (&src)[PV]) {
 #pragma unroll
