@@ -76,36 +76,42 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
     const _Float16* Vz = a.V + (i64)by * a.vchunk;
     const float* Xz = a.X + 2 * ((i64)by * a.xchunk);
     const float sx = split_scale(a.xmax);
-    // V' item u: 8-wide k group vh of combined (plane, row) R0 + (NPT / 8) u
-    // over the 16 FS rows of each plane that are multiplied (the rows of the
-    // padding fragment are never read)
+    // V' items: the M rows of each plane whose products are written, as
+    // combined rows R = (plane) M + (row) < 2 M.  Item u of a lane is the
+    // 8-wide k group vh of combined row R0 + 32 u (R0 = 8 pw + lane / 8); a
+    // wave takes the NI items whose 32-row groups start below 2 M (FS - 1 or
+    // FS of them, a compile-time count: no load instruction is issued for
+    // rows that are never used).  Lanes past 2 M inside the last group read
+    // plane 1's row M - 1 and write rows past M of plane 1; the LDS rows past
+    // M of either plane are multiplied only into output rows that are never
+    // written.
     const int vh = 8 * (pt & 7), R0 = pt >> 3;
+    const int M = a.M;
     auto vrow = [&](int u, int& pl, int& r) {
       const int R = R0 + (NPT / 8) * u;
-      pl = R >= 16 * FS ? 1 : 0;
-      r = R - pl * 16 * FS;
+      pl = R >= M ? 1 : 0;
+      r = min(R - pl * M, 16 * FSP - 1);
     };
-    // Loads only clamp their addresses: rows past M read row M - 1 (their
-    // products land in output rows that are never written), k past the chunk
-    // reads its last 8-group (the chunk padding is zero), slabs past the end
-    // are never multiplied.  Each load is the chunk's base plus a 32-bit byte
-    // offset (both planes of V' span under 1.1e9 bytes for N <= 128).
+    // Loads only clamp their addresses: k past the chunk reads its last
+    // 8-group (the chunk padding is zero), slabs past the end are never
+    // multiplied.  Each load is the chunk's base plus a 32-bit byte offset
+    // (both planes of V' span under 1.1e9 bytes for N <= 128).
     unsigned vro[PV];
 #pragma unroll
     for (int u = 0; u < PV; ++u) {
       int pl, r;
       vrow(u, pl, r);
-      vro[u] = 2u * (unsigned)(pl * a.vplane + (i64)min(r, a.M - 1) * a.ldv);
+      vro[u] = 2u * (unsigned)(pl * a.vplane + (i64)min(r, M - 1) * a.ldv);
     }
-    auto load_v = [&](int s, hx8 (&dst)[PV]) {
+    auto load_v = [&](auto NIc, int s, hx8 (&dst)[PV]) {
       const unsigned ko = 2u * (unsigned)min(s * KS + vh, (int)a.vchunk - 8);
       const char* base = reinterpret_cast<const char*>(Vz);
 #pragma unroll
-      for (int u = 0; u < PV; ++u) dst[u] = *reinterpret_cast<const hx8*>(base + (vro[u] + ko));
+      for (int u = 0; u < decltype(NIc)::value; ++u) dst[u] = *reinterpret_cast<const hx8*>(base + (vro[u] + ko));
     };
-    auto store_v = [&](int buf, const hx8 (&src)[PV]) {
+    auto store_v = [&](auto NIc, int buf, const hx8 (&src)[PV]) {
 #pragma unroll
-      for (int u = 0; u < PV; ++u) {
+      for (int u = 0; u < decltype(NIc)::value; ++u) {
         int pl, r;
         vrow(u, pl, r);
         *reinterpret_cast<hx8*>(&sV[buf][pl][r][vh]) = src[u];
@@ -151,35 +157,41 @@ __device__ __forceinline__ void r4_body(const R4Args& a, int bx, int by) {
     // the set being stored.  (Scheduling fences: the compiler would otherwise
     // hoist the register-only split of the next set above the barrier and wait
     // for its loads a slab early.)
-    hx8 va[PV], vb[PV];
-    float4 ca[PC], cb[PC];
-    if (nslab > 0) {
-      load_v(0, va);
-      load_c(0, ca);
-      load_v(1, vb);
-      load_c(1, cb);
-      store_v(0, va);
-      store_c(0, 0, ca);
-      load_v(2, va);
-      load_c(2, ca);
-    }
+    auto produce = [&](auto NIc) {
+      hx8 va[PV], vb[PV];
+      float4 ca[PC], cb[PC];
+      if (nslab > 0) {
+        load_v(NIc, 0, va);
+        load_c(0, ca);
+        load_v(NIc, 1, vb);
+        load_c(1, cb);
+        store_v(NIc, 0, va);
+        store_c(0, 0, ca);
+        load_v(NIc, 2, va);
+        load_c(2, ca);
+      }
 #pragma unroll 1
-    for (int s = 0; s < nslab; s += 2) {
-      __syncthreads();                                  // slab s in buffer 0; buffer 1 free
-      __builtin_amdgcn_sched_barrier(0);
-      store_v(1, vb);
-      store_c(1, s + 1, cb);
-      load_v(s + 3, vb);
-      load_c(s + 3, cb);
-      __builtin_amdgcn_sched_barrier(0);
-      __syncthreads();                                  // slab s + 1 in buffer 1; buffer 0 free
-      __builtin_amdgcn_sched_barrier(0);
-      store_v(0, va);
-      store_c(0, s + 2, ca);
-      load_v(s + 4, va);
-      load_c(s + 4, ca);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+      for (int s = 0; s < nslab; s += 2) {
+        __syncthreads();                                // slab s in buffer 0; buffer 1 free
+        __builtin_amdgcn_sched_barrier(0);
+        store_v(NIc, 1, vb);
+        store_c(1, s + 1, cb);
+        load_v(NIc, s + 3, vb);
+        load_c(s + 3, cb);
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();                                // slab s + 1 in buffer 1; buffer 0 free
+        __builtin_amdgcn_sched_barrier(0);
+        store_v(NIc, 0, va);
+        store_c(0, s + 2, ca);
+        load_v(NIc, s + 4, va);
+        load_c(s + 4, ca);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    // items of this wave (wave-uniform): FS - 1 or FS, as M > 16 (FS - 1)
+    const int ni = (2 * M - 8 * pw + 31) / 32;
+    if (ni >= PV) produce(std::integral_constant<int, PV>{});
+    else produce(std::integral_constant<int, PV - 1>{});
     return;
   }
 
