@@ -771,6 +771,51 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
   };
 
   // ---- write one finished tile ----
+  // Paired form (float32 output, rows from the shared operand, unit column
+  // stride, even row stride and column count, 16-byte aligned output): the
+  // lanes of columns 2c and 2c + 1 exchange half of their accumulators (a DPP
+  // swap), so that each lane holds two rows of the column pair and writes
+  // each row's pair as one 16-byte store: half the store instructions of one
+  // 8-byte store per element.  Out-of-range pairs go to the sink, so every
+  // tile issues the same 2 FS stores.
+  // (used where the streamed operand is real, as in the first contraction)
+  constexpr bool PAIRABLE = SA && !XC && std::is_same<OutT, float>::value && std::is_same<T, float>::value;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  auto epilogue_pairs = [&](int tx) {
+    const int x0 = tx * XT + w * 16;
+    const float usc = (float)unscale;                        // a power of two: exact
+    const int par = lr & 1;
+    const int n0 = x0 + (lr & ~1);
+    const bool nv = n0 < xlim;                               // n0 + 1 < xlim as well (xlim even)
+    f4v* sink = reinterpret_cast<f4v*>(g.trash) + lane;
+#pragma unroll
+    for (int i = 0; i < FS; ++i) {
+      // DPP quad permutation [1, 0, 3, 2]: exchange with the neighbouring lane
+      float sr_[2], si_[2], rr_[2], ri_[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        sr_[j] = par ? cr[i][j] : cr[i][j + 2];
+        si_[j] = par ? ci[i][j] : ci[i][j + 2];
+        rr_[j] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(sr_[j]), 0xB1, 0xF, 0xF, false));
+        ri_[j] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(si_[j]), 0xB1, 0xF, 0xF, false));
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // rows 4 grp + 2 par + j; columns n0 (lo) and n0 + 1 (hi)
+        const int m = s0 + i * 16 + 4 * grp + 2 * par + j;
+        const float lre = par ? rr_[j] : cr[i][j], lim = par ? ri_[j] : ci[i][j];
+        const float hre = par ? cr[i][2 + j] : rr_[j], him = par ? ci[i][2 + j] : ri_[j];
+        f4v v;
+        v[0] = lre * usc;
+        v[1] = lim * usc;
+        v[2] = hre * usc;
+        v[3] = him * usc;
+        const bool ok = nv && m < slim;
+        *opaque(ok ? reinterpret_cast<f4v*>(Cb + 2 * ((i64)m * g.sCm + n0)) : sink) = v;
+        if constexpr (H) mx = fmaxf(mx, ok ? fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))) : 0.f);
+      }
+    }
+  };
   auto epilogue = [&](int tx) {
     const int x0 = tx * XT + w * 16;
     const T usc = (T)unscale;                                // a power of two: exact
@@ -832,27 +877,67 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
   // completes in order, so a load issued after the stores could only be
   // waited for together with them)
   XT_ ta, tb;
-  int tx = pp;
-  if (tx < tiles_x) {
-    load_sg(tx, 0, ta);
-    load_sg(tx, 1, tb);
-    // as many sink stores as one tile's epilogue: the loop is entered with the
-    // same memory-operation sequence as from its back edge
-    typedef OutT o2 __attribute__((ext_vector_type(2)));
-    o2 z;
-    z[0] = z[1] = (OutT)0;
+  // PAIRS: the paired epilogue (a uniform choice for the whole launch, so each
+  // loop issues a fixed sequence of memory operations)
+  auto run_tiles = [&](auto PAIRS) {
+    constexpr bool P = decltype(PAIRS)::value;
+    int tx = pp;
+    if (tx < tiles_x) {
+      load_sg(tx, 0, ta);
+      load_sg(tx, 1, tb);
+      // as many sink stores as one tile's epilogue: the loop is entered with
+      // the same memory-operation sequence as from its back edge
+      if constexpr (P) {
 #pragma unroll
-    for (int e = 0; e < FS * 4; ++e) *opaque(reinterpret_cast<o2*>(g.trash) + lane) = z;
-  }
-  for (; tx < tiles_x; tx += npersist) {
-    zero_arr(cr);
-    zero_arr(ci);
-    const bool more = tx + npersist < tiles_x;
-    compute_sg(0, ta);
-    if (more) load_sg(tx + npersist, 0, ta);
-    compute_sg(1, tb);
-    if (more) load_sg(tx + npersist, 1, tb);
-    epilogue(tx);
+        for (int e = 0; e < FS * 2; ++e) *opaque(reinterpret_cast<f4v*>(g.trash) + lane) = f4v{0.f, 0.f, 0.f, 0.f};
+      } else {
+        typedef OutT o2 __attribute__((ext_vector_type(2)));
+        o2 z;
+        z[0] = z[1] = (OutT)0;
+#pragma unroll
+        for (int e = 0; e < FS * 4; ++e) *opaque(reinterpret_cast<o2*>(g.trash) + lane) = z;
+      }
+    }
+    for (; tx < tiles_x; tx += npersist) {
+      zero_arr(cr);
+      zero_arr(ci);
+      const bool more = tx + npersist < tiles_x;
+      compute_sg(0, ta);
+      if (more) load_sg(tx + npersist, 0, ta);
+      compute_sg(1, tb);
+      if (more) load_sg(tx + npersist, 1, tb);
+      if constexpr (P) epilogue_pairs(tx);
+      else epilogue(tx);
+    }
+  };
+  if constexpr (PAIRABLE) {
+    const bool pairs = g.sCn == 1 && (g.sCm & 1) == 0 && (xlim & 1) == 0 &&
+                       (reinterpret_cast<uintptr_t>(Cb) & 15) == 0;
+    if (pairs) run_tiles(std::true_type{});
+    else run_tiles(std::false_type{});
+  } else {
+    int tx = pp;
+    if (tx < tiles_x) {
+      load_sg(tx, 0, ta);
+      load_sg(tx, 1, tb);
+      // as many sink stores as one tile's epilogue: the loop is entered with
+      // the same memory-operation sequence as from its back edge
+      typedef OutT o2 __attribute__((ext_vector_type(2)));
+      o2 z;
+      z[0] = z[1] = (OutT)0;
+#pragma unroll
+      for (int e = 0; e < FS * 4; ++e) *opaque(reinterpret_cast<o2*>(g.trash) + lane) = z;
+    }
+    for (; tx < tiles_x; tx += npersist) {
+      zero_arr(cr);
+      zero_arr(ci);
+      const bool more = tx + npersist < tiles_x;
+      compute_sg(0, ta);
+      if (more) load_sg(tx + npersist, 0, ta);
+      compute_sg(1, tb);
+      if (more) load_sg(tx + npersist, 1, tb);
+      epilogue(tx);
+    }
   }
   if constexpr (H) {
     if (g.cmax) {
