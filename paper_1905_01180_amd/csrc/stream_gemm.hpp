@@ -910,35 +910,11 @@ __device__ __forceinline__ void stream1_body(const StreamArgs& g, int bx, int by
       else epilogue(tx);
     }
   };
-  if constexpr (PAIRABLE) {
-    const bool pairs = g.sCn == 1 && (g.sCm & 1) == 0 && (xlim & 1) == 0 &&
-                       (reinterpret_cast<uintptr_t>(Cb) & 15) == 0;
-    if (pairs) run_tiles(std::true_type{});
-    else run_tiles(std::false_type{});
-  } else {
-    int tx = pp;
-    if (tx < tiles_x) {
-      load_sg(tx, 0, ta);
-      load_sg(tx, 1, tb);
-      // as many sink stores as one tile's epilogue: the loop is entered with
-      // the same memory-operation sequence as from its back edge
-      typedef OutT o2 __attribute__((ext_vector_type(2)));
-      o2 z;
-      z[0] = z[1] = (OutT)0;
-#pragma unroll
-      for (int e = 0; e < FS * 4; ++e) *opaque(reinterpret_cast<o2*>(g.trash) + lane) = z;
-    }
-    for (; tx < tiles_x; tx += npersist) {
-      zero_arr(cr);
-      zero_arr(ci);
-      const bool more = tx + npersist < tiles_x;
-      compute_sg(0, ta);
-      if (more) load_sg(tx + npersist, 0, ta);
-      compute_sg(1, tb);
-      if (more) load_sg(tx + npersist, 1, tb);
-      epilogue(tx);
-    }
-  }
+  bool pairs = false;
+  if constexpr (PAIRABLE)
+    pairs = g.sCn == 1 && (g.sCm & 1) == 0 && (xlim & 1) == 0 && (reinterpret_cast<uintptr_t>(Cb) & 15) == 0;
+  if (pairs) run_tiles(std::integral_constant<bool, PAIRABLE>{});
+  else run_tiles(std::false_type{});
   if constexpr (H) {
     if (g.cmax) {
       mx = wave_max(mx);
