@@ -23,7 +23,8 @@ def dev(x):
 
 
 @pytest.mark.parametrize("n,b", [(1, 2), (15, 2), (16, 3), (31, 2), (32, 1), (33, 2), (48, 1), (63, 1), (70, 1),
-                                 (97, 1), (100, 1), (100, 3), (101, 2), (112, 1), (112, 2), (113, 1)])
+                                 (81, 1), (96, 2), (97, 1), (100, 1), (100, 3), (101, 2), (112, 1), (112, 2),
+                                 (113, 1)])
 def test_fused_matches_oracle_and_two_launch_path(n, b):
     from paper_1905_01180_amd import _lib
     g = np.random.default_rng(3000 + n)
