@@ -18,7 +18,8 @@
 //   * C: every load instruction of a wave covers two whole 512-byte column
 //     runs (coalesced), the values are split and stored as four float16
 //     planes (re hi, re lo, im hi, im lo);
-//   * V': 8-wide k groups of every row, both planes.
+//   * V': 8-wide k groups of both planes' rows below M (rows past M only
+//     reach output rows that are never written and are not loaded).
 // One barrier per slab.
 #pragma once
 #include <hip/hip_runtime.h>
